@@ -1,0 +1,206 @@
+/*
+ * pjds.h -- C interface of libpjds, sparse matrix-vector multiplication in the padded
+ * jagged diagonals storage (pJDS) format on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: Kreutzer, Hager, Wellein, Fehske, Basermann, Bishop, "Sparse matrix-vector
+ * multiplication on GPGPU clusters: a new storage format and a scalable implementation",
+ * arXiv:1112.5588.  Section numbers below refer to it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Types      Row pointers and every offset are int64_t; column indices, permutations and
+ *            row lengths are int32_t (so n_rows, n_cols < 2^31).  Matrix values, x and y
+ *            are double (dtype PJDS_F64) or float (PJDS_F32); one dtype per call.
+ * Memory     "host" arguments are ordinary CPU pointers; "device" arguments are HIP device
+ *            pointers on the current device.  The caller allocates and frees every buffer;
+ *            the library keeps no pointer beyond a call, except inside a batch handle
+ *            (pjds_batch_*), which the caller destroys explicitly.
+ * Streams    `stream` is a hipStream_t passed as void* (NULL = the default stream).  Device
+ *            work is enqueued on it and the call returns without synchronising.
+ * Errors     Every function returns PJDS_OK (0) or a negative PJDS_ERR_* code and leaves a
+ *            message for pjds_last_error() (thread-local).  Arguments are validated before
+ *            any output is written, so a failing call writes nothing.  Faults inside a
+ *            kernel surface at the caller's next synchronisation, not here.
+ * Threads    All functions are reentrant; concurrent calls on one device are safe unless
+ *            they share an output or a workspace.
+ */
+#ifndef PJDS_H
+#define PJDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define PJDS_OK               0
+#define PJDS_ERR_ARG         (-1)  /* bad size, flag, dtype, block height or NULL pointer   */
+#define PJDS_ERR_INDEX       (-2)  /* row_ptr not monotone / not starting at 0, column out of range */
+#define PJDS_ERR_OVERFLOW    (-3)  /* a size or offset exceeds what the format can address   */
+#define PJDS_ERR_NOMEM       (-4)  /* host allocation failed                                 */
+#define PJDS_ERR_HIP         (-5)  /* the HIP runtime reported an error (launch, graph, event) */
+#define PJDS_ERR_UNSUPPORTED (-6)  /* valid request outside what this build implements       */
+
+/* ---- value types ------------------------------------------------------------------- */
+#define PJDS_F64 0
+#define PJDS_F32 1
+
+/* ---- flags ------------------------------------------------------------------------- */
+/* Conversion flags (pjds_plan). */
+#define PJDS_LAYOUT_JD     0x0u  /* column j of the whole matrix contiguous, Listing 2's col_start
+                                    addressing; needs a global sort                              */
+#define PJDS_LAYOUT_BLOCK  0x1u  /* every block its own b_r x M_b column-major tile; any sort window */
+#define PJDS_SYMMETRIC     0x2u  /* renumber columns into the permuted basis (square matrices):
+                                    the kernel then computes (P A P^T)(P x), the way the paper runs
+                                    an iterative solver entirely in the permuted basis (Sect. 2.1)  */
+/* Product flags (pjds_spmv, pjds_spmmv). */
+#define PJDS_Y_PERMUTED    0x4u  /* write y in the permuted row basis: y[i] = (A x)[perm[i]],
+                                    coalesced; default scatters y to the original row order       */
+#define PJDS_NO_XCD_REMAP  0x8u  /* keep the hardware's round-robin block-to-XCD order instead of
+                                    giving each XCD a contiguous range of row blocks               */
+
+/* ---- pJDS -------------------------------------------------------------------------- */
+/*
+ * Sizes of a pJDS matrix, filled by pjds_plan (Sect. 2.1, "sort" and "pad" steps).
+ *
+ * Rows are sorted by their number of non-zeros, longest first; rows of equal length keep
+ * their original order.  With sort_window < n_rows the sort happens only inside each
+ * window of sort_window consecutive original rows (windows hold whole blocks).  The row
+ * count is padded with empty rows to n_pad, a multiple of the block height b_r, and every
+ * block of b_r consecutive sorted rows is padded to its longest row M_b; the stored entry
+ * count is nnz_stored = b_r * sum_b M_b.  Padding slots hold value 0 and column 0.
+ *
+ * Offsets: JD layout -> n_offsets = max_row_len + 1 entries col_start[j] (start of jagged
+ * diagonal j; entry j of sorted row i is at col_start[j] + i, as in Listing 2).  Block
+ * layout -> n_offsets = n_blocks + 1 entries block_start[b] (entry j of sorted row i is at
+ * block_start[i / b_r] + j * b_r + i % b_r).  The last offset equals nnz_stored.
+ *
+ * Long rows: wave groups (64 consecutive sorted rows, one GPU wavefront) whose longest row
+ * exceeds split_len are processed as n_chunks work items of at most split_len entries
+ * each, whose partial sums are combined in a fixed order; their schedule (4 int32 per work
+ * item) is written by pjds_convert and they need a device workspace (pjds_workspace_size).
+ */
+typedef struct pjds_info {
+    int64_t  n_rows, n_cols;
+    int64_t  n_pad;          /* rows after padding, multiple of block_height             */
+    int64_t  n_blocks;       /* n_pad / block_height                                      */
+    int64_t  nnz;            /* entries of the input                                       */
+    int64_t  nnz_stored;     /* entries of the padded format                               */
+    int64_t  sort_window;    /* effective window; n_rows for a global sort                 */
+    int64_t  n_offsets;      /* entries of the offsets array                               */
+    int32_t  block_height;   /* b_r: 32, 64 or 128                                         */
+    int32_t  max_row_len;    /* longest row                                                */
+    uint32_t flags;          /* PJDS_LAYOUT_* | PJDS_SYMMETRIC, as planned                 */
+    int32_t  split_len;      /* long-row threshold and work-item length; 0 = never split  */
+    int64_t  n_chunks;       /* work items of split wave groups (0 if none)               */
+    int64_t  n_split_groups; /* wave groups that are split                                 */
+} pjds_info;
+
+/*
+ * Validate row_ptr (host, n_rows + 1 entries, row_ptr[0] = 0, non-decreasing) and size the
+ * pJDS format.  block_height must be 32, 64 or 128 (the MI355X wavefront is 64 lanes).
+ * sort_window <= 0 or >= n_rows means a global sort; otherwise it must be a positive
+ * multiple of 64 and of block_height.  flags: PJDS_LAYOUT_* | PJDS_SYMMETRIC; the JD layout
+ * needs a global sort.  split_len < 0 disables long-row splitting, 0 picks the default
+ * (128), > 0 sets it (a multiple of 8).
+ * Errors: ERR_ARG, ERR_INDEX, ERR_OVERFLOW (nnz_stored or n_pad >= 2^31 rows).
+ */
+int pjds_plan(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, int32_t block_height,
+              int64_t sort_window, uint32_t flags, int32_t split_len, pjds_info *out);
+
+/*
+ * Build the pJDS arrays on the host (Sect. 2.1; addressing of Listing 2).
+ *   row_ptr  [n_rows+1], col_idx [nnz], val [nnz] (dtype)      host, input CSR
+ *   perm     [n_rows]     int32   host, out: perm[i] = original row of sorted row i
+ *   row_len  [n_pad]      int32   host, out: length of sorted row i, 0 for padding rows
+ *   offsets  [n_offsets]  int64   host, out: col_start (JD) or block_start (block)
+ *   col_p    [nnz_stored] int32   host, out: column index per stored entry (padding 0;
+ *                                 with PJDS_SYMMETRIC the renumbered column invperm[col])
+ *   val_p    [nnz_stored] dtype   host, out: value per stored entry (padding 0), bit copies
+ *   sched    [4*n_chunks] int32   host, out: long-row work items; may be NULL if n_chunks = 0
+ * `info` must come from pjds_plan on the same row_ptr.  Column indices are checked to lie
+ * in [0, n_cols) before anything is written.  Deterministic; uses several host threads.
+ */
+int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *col_idx,
+                 const void *val, int32_t dtype, int32_t *perm, int32_t *row_len,
+                 int64_t *offsets, int32_t *col_p, void *val_p, int32_t *sched);
+
+/* Device workspace for the long-row work items: bytes needed (0 when n_chunks == 0). */
+int pjds_workspace_size(const pjds_info *info, int32_t dtype, int64_t *bytes);
+
+/* Zero the workspace's completion counters (once after allocating it; the product leaves
+ * them zero again).  Enqueued on `stream`; uses a kernel, not a memset. */
+int pjds_workspace_init(const pjds_info *info, int32_t dtype, void *d_work, void *stream);
+
+/*
+ * y = A x on the device with the pJDS arrays (Listing 2; one GPU lane per sorted row, one
+ * 64-lane wavefront per 64 consecutive sorted rows).
+ *   d_row_len, d_offsets, d_col_p, d_val_p  device copies of pjds_convert's outputs
+ *   d_perm    device perm; may be NULL when flags has PJDS_Y_PERMUTED
+ *   d_sched, d_work  device schedule and workspace; may be NULL when info->n_chunks == 0
+ *   d_x       [n_cols] dtype, device: in the original column basis, or in the permuted
+ *             basis (x_p[i] = x[perm[i]]) if the matrix was converted with PJDS_SYMMETRIC
+ *   d_y       [n_rows] dtype, device, out: original row order, or the permuted order with
+ *             PJDS_Y_PERMUTED.  Written, never read.
+ * Sums run over each row's entries in stored order with fused multiply-add; long rows are
+ * summed per work item and the partial sums added in item order, so results are
+ * bitwise reproducible from run to run.  Padding never enters the arithmetic.
+ */
+int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+              const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+              const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x, void *d_y,
+              uint32_t flags, void *stream);
+
+/*
+ * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v].
+ * Each work item loads a matrix entry once and applies it to `vectors_per_tile` (1, 2, 4
+ * or 8) consecutive right-hand sides, so the matrix is streamed ceil(k / t) times.
+ * Arguments as pjds_spmv; k >= 1.  Long rows are not split here (d_sched unused).
+ */
+int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+               const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+               int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
+               uint32_t flags, void *stream);
+
+/* ---- ELLPACK-R (Sect. 2.1, Listing 1) ---------------------------------------------- */
+/*
+ * Rows keep their order; the non-zeros of each row are shifted left and the
+ * n_pad x max_row_len rectangle is stored column by column: entry j of row i at
+ * j * n_pad + i, with n_pad = n_rows rounded up to a multiple of 64.  rowmax[i] holds the
+ * length of row i.  pjds_info is reused: block_height = 64, nnz_stored = n_pad*max_row_len,
+ * n_offsets = 0.  ellr_plan reports the size even when it is too large to allocate; the
+ * caller decides.  ERR_OVERFLOW if nnz_stored does not fit int64.
+ */
+int ellr_plan(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, pjds_info *out);
+int ellr_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *col_idx,
+                 const void *val, int32_t dtype, int32_t *rowmax, int32_t *col_e, void *val_e);
+/* y = A x with the ELLPACK-R arrays (Listing 1): one lane per row, y in row order. */
+int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_col_e,
+              const void *d_val_e, int32_t dtype, const void *d_x, void *d_y, void *stream);
+
+/* ---- CSR on the GPU (the format of the paper's CPU comparison, Table 1) -------------- */
+/*
+ * y = A x straight from CSR device arrays.  variant 1: one lane per row (scalar);
+ * 4, 16 or 64: that many lanes per row, each summing a strided subset of the row, then a
+ * fixed-order butterfly reduction (vector).  Deterministic.
+ */
+int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int32_t *d_col,
+             const void *d_val, int32_t dtype, const void *d_x, void *d_y, int32_t variant,
+             void *stream);
+
+/* ---- measurement helpers ------------------------------------------------------------ */
+/* Stream probes for the achievable bandwidth ceiling: mode 0 reads n doubles and writes one
+ * value per workgroup to d_out (reduction), mode 1 copies n doubles d_in -> d_out. */
+int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------------- */
+const char *pjds_last_error(void);
+/* Library version string. */
+const char *pjds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PJDS_H */

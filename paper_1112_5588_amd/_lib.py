@@ -1,0 +1,224 @@
+"""ctypes binding of libpjds (include/pjds.h): the same entry points, argument marshalling only.
+
+Host arrays are numpy arrays; device arrays are torch tensors on a ROCm device (used only
+as device memory); streams are ``torch.cuda.Stream`` objects or raw ``hipStream_t``
+integers.  Every call checks the status and raises ``PjdsError`` with the library's
+message.  Loading fails loudly if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpjds.so")
+
+PJDS_OK = 0
+PJDS_ERR_ARG = -1
+PJDS_ERR_INDEX = -2
+PJDS_ERR_OVERFLOW = -3
+PJDS_ERR_NOMEM = -4
+PJDS_ERR_HIP = -5
+PJDS_ERR_UNSUPPORTED = -6
+
+PJDS_F64 = 0
+PJDS_F32 = 1
+
+PJDS_LAYOUT_JD = 0x0
+PJDS_LAYOUT_BLOCK = 0x1
+PJDS_SYMMETRIC = 0x2
+PJDS_Y_PERMUTED = 0x4
+PJDS_NO_XCD_REMAP = 0x8
+
+
+class PjdsError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+class pjds_info(ctypes.Structure):
+    _fields_ = [
+        ("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("n_pad", ctypes.c_int64),
+        ("n_blocks", ctypes.c_int64), ("nnz", ctypes.c_int64), ("nnz_stored", ctypes.c_int64),
+        ("sort_window", ctypes.c_int64), ("n_offsets", ctypes.c_int64),
+        ("block_height", ctypes.c_int32), ("max_row_len", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("split_len", ctypes.c_int32),
+        ("n_chunks", ctypes.c_int64), ("n_split_groups", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_ip = ctypes.POINTER(pjds_info)
+
+# name -> argtypes (all return int unless listed in _RESTYPE)
+_SIGS = {
+    "pjds_plan": [_i64, _i64, _vp, _i32, _i64, _u32, _i32, _ip],
+    "pjds_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
+    "pjds_workspace_size": [_ip, _i32, ctypes.POINTER(ctypes.c_int64)],
+    "pjds_workspace_init": [_ip, _i32, _vp, _vp],
+    "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
+    "ellr_plan": [_i64, _i64, _vp, _ip],
+    "ellr_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "csr_spmv": [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp],
+    "pjds_probe": [_i32, _vp, _vp, _i64, _vp],
+    "pjds_last_error": [],
+    "pjds_version": [],
+}
+_RESTYPE = {"pjds_last_error": ctypes.c_char_p, "pjds_version": ctypes.c_char_p}
+EXPORTED = tuple(_SIGS)
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1112_5588_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _RESTYPE.get(name, ctypes.c_int)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != PJDS_OK:
+        raise PjdsError(rc, where, pjds_last_error())
+
+
+def _host(a, dtype=None):
+    """Pointer of a contiguous numpy array (None -> NULL)."""
+    if a is None:
+        return None
+    if dtype is not None and a.dtype != np.dtype(dtype):
+        raise TypeError(f"expected {np.dtype(dtype)}, got {a.dtype}")
+    if not a.flags.c_contiguous:
+        raise ValueError("host arrays must be C-contiguous")
+    return a.ctypes.data if a.size else a.ctypes.data or None
+
+
+def _dev(t):
+    """Device pointer of a contiguous torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device arrays must be torch tensors on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous")
+    return t.data_ptr() or None
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _dtype_code(dt) -> int:
+    name = str(dt).replace("torch.", "")
+    if name in ("float64", "double"):
+        return PJDS_F64
+    if name in ("float32", "float"):
+        return PJDS_F32
+    raise TypeError(f"unsupported value type {dt}")
+
+
+# ------------------------------------------------------------------ entry points
+
+def pjds_last_error() -> str:
+    return (lib().pjds_last_error() or b"").decode()
+
+
+def pjds_version() -> str:
+    return lib().pjds_version().decode()
+
+
+def pjds_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray, block_height: int = 64,
+              sort_window: int = 0, flags: int = 0, split_len: int = 0) -> pjds_info:
+    info = pjds_info()
+    _check(lib().pjds_plan(n_rows, n_cols, _host(row_ptr, np.int64), block_height, sort_window,
+                           flags, split_len, ctypes.byref(info)), "pjds_plan")
+    return info
+
+
+def pjds_convert(info: pjds_info, row_ptr, col_idx, val, perm, row_len, offsets, col_p, val_p,
+                 sched=None) -> None:
+    _check(lib().pjds_convert(ctypes.byref(info), _host(row_ptr, np.int64), _host(col_idx, np.int32),
+                              _host(val), _dtype_code(val.dtype), _host(perm, np.int32),
+                              _host(row_len, np.int32), _host(offsets, np.int64),
+                              _host(col_p, np.int32), _host(val_p), _host(sched, np.int32)),
+           "pjds_convert")
+
+
+def pjds_workspace_size(info: pjds_info, dtype) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().pjds_workspace_size(ctypes.byref(info), _dtype_code(dtype), ctypes.byref(out)),
+           "pjds_workspace_size")
+    return out.value
+
+
+def pjds_workspace_init(info: pjds_info, dtype, d_work, stream=None) -> None:
+    _check(lib().pjds_workspace_init(ctypes.byref(info), _dtype_code(dtype), _dev(d_work),
+                                     _stream(stream)), "pjds_workspace_init")
+
+
+def pjds_spmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work,
+              d_x, d_y, flags: int = 0, stream=None) -> None:
+    _check(lib().pjds_spmv(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                           _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
+                           _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), flags, _stream(stream)),
+           "pjds_spmv")
+
+
+def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,
+               vectors_per_tile: int, d_X, d_Y, flags: int = 0, stream=None) -> None:
+    _check(lib().pjds_spmmv(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                            _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
+                            vectors_per_tile, _dev(d_X), _dev(d_Y), flags, _stream(stream)),
+           "pjds_spmmv")
+
+
+def ellr_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray) -> pjds_info:
+    info = pjds_info()
+    _check(lib().ellr_plan(n_rows, n_cols, _host(row_ptr, np.int64), ctypes.byref(info)), "ellr_plan")
+    return info
+
+
+def ellr_convert(info: pjds_info, row_ptr, col_idx, val, rowmax, col_e, val_e) -> None:
+    _check(lib().ellr_convert(ctypes.byref(info), _host(row_ptr, np.int64), _host(col_idx, np.int32),
+                              _host(val), _dtype_code(val.dtype), _host(rowmax, np.int32),
+                              _host(col_e, np.int32), _host(val_e)), "ellr_convert")
+
+
+def ellr_spmv(info: pjds_info, d_rowmax, d_col_e, d_val_e, d_x, d_y, stream=None) -> None:
+    _check(lib().ellr_spmv(ctypes.byref(info), _dev(d_rowmax), _dev(d_col_e), _dev(d_val_e),
+                           _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), _stream(stream)), "ellr_spmv")
+
+
+def csr_spmv(n_rows: int, n_cols: int, d_row_ptr, d_col, d_val, d_x, d_y, variant: int = 1,
+             stream=None) -> None:
+    _check(lib().csr_spmv(n_rows, n_cols, _dev(d_row_ptr), _dev(d_col), _dev(d_val),
+                          _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), variant, _stream(stream)),
+           "csr_spmv")
+
+
+def pjds_probe(mode: int, d_in, d_out, n: int, stream=None) -> None:
+    _check(lib().pjds_probe(mode, _dev(d_in), _dev(d_out), n, _stream(stream)), "pjds_probe")

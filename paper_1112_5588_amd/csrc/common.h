@@ -1,0 +1,53 @@
+// Internal helpers shared by the host code and the kernel launchers of libpjds.
+#pragma once
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/pjds.h"
+
+namespace pjds {
+
+// Thread-local message of the last failing call (pjds_last_error).
+void set_error(const char *fmt, ...);
+const char *get_error();
+
+// Record a message and return the status code, for `return fail(PJDS_ERR_ARG, "...")`.
+int fail(int code, const char *fmt, ...);
+
+// Number of host worker threads for conversion: PJDS_NUM_THREADS, else the hardware count
+// (at most 32).
+int host_threads();
+
+// Run body(t, begin, end) over [0, n) split into contiguous ranges, one per thread.
+template <class F>
+void parallel_ranges(int64_t n, F body);
+
+constexpr int kWave = 64;  // MI355X wavefront width
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace pjds
+
+#include <thread>
+#include <vector>
+
+template <class F>
+void pjds::parallel_ranges(int64_t n, F body) {
+    int nt = host_threads();
+    if (n < 65536 || nt <= 1) {
+        body(0, int64_t(0), n);
+        return;
+    }
+    if (nt > n) nt = int(n);
+    std::vector<std::thread> pool;
+    int64_t step = ceil_div(n, nt);
+    for (int t = 0; t < nt; ++t) {
+        int64_t b = t * step, e = b + step < n ? b + step : n;
+        if (b >= e) break;
+        pool.emplace_back([=] { body(t, b, e); });
+    }
+    for (auto &th : pool) th.join();
+}

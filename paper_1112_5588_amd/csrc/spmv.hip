@@ -1,0 +1,495 @@
+// Sparse matrix-vector kernels for MI355X (gfx950): pJDS (Listing 2 of Kreutzer et al.,
+// arXiv:1112.5588), ELLPACK-R (Listing 1), CSR, and the many-right-hand-side pJDS product.
+//
+// Mapping.  One lane owns one (sorted) row; one 64-lane wavefront owns 64 consecutive rows
+// (a "wave group").  With the block height b_r = 64 a wave group is exactly one pJDS block,
+// so every lane of a wave loops to the same block maximum M_b and the stored column
+// segment of that block (64 values, 64 indices) is one coalesced 512 B + 256 B access per
+// step.  b_r = 32 puts two blocks in a wave, b_r = 128 spreads a block over two waves; the
+// loop bound is always the wave's own longest row, and each lane masks its arithmetic with
+// its own row length, so padding never enters a sum.
+//
+// Streams.  Values and column indices are read exactly once per product, so they are
+// loaded non-temporally; x goes through the normal cached path (it is re-read by every
+// row that references it).  Workgroups are renumbered so that each XCD (8 per MI355X, each
+// with its own L2) processes one contiguous range of row blocks, which keeps the x window
+// of neighbouring blocks in that XCD's L2.
+//
+// Long rows.  Wave groups whose longest row exceeds split_len are cut into work items of
+// split_len steps, scheduled first.  Each item writes its 64 partial sums to the workspace;
+// the item that completes a group last (device-scope counter) adds the partials in item
+// order and stores y, then resets the counter.  The order of additions is therefore fixed
+// and results are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "common.h"
+
+namespace pjds {
+namespace {
+
+constexpr int kBlock = 256;               // threads per workgroup
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kUnroll = 8;                // independent entries in flight per lane
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
+    // Hardware hands workgroup b to XCD b % 8; give XCD x the contiguous logical range
+    // [x*q + min(x, r), ...) of length q + (x < r).  A bijection on [0, grid).
+    const uint32_t x = b % kXcds, k = b / kXcds, q = grid / kXcds, r = grid % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
+    return (flags & PJDS_NO_XCD_REMAP) ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+
+// Sum of row entries j in [j0, j1) for the calling lane (row i, length len), Listing 2's
+// inner loop.  j1 is wave-uniform and <= the wave's longest row.
+template <class T, bool JD, int BR>
+__device__ __forceinline__ T row_range_sum(int64_t i, int len, int j0, int j1,
+                                           const int64_t *__restrict__ offsets,
+                                           const int32_t *__restrict__ col_p,
+                                           const T *__restrict__ val_p,
+                                           const T *__restrict__ x) {
+    // Block layout: entry j of row i at block_start[i / BR] + j*BR + i % BR.
+    const int64_t base = JD ? i : offsets[i / BR] + (i % BR);
+    T acc = T(0);
+    for (int jb = j0; jb < j1; jb += kUnroll) {
+        T v[kUnroll];
+        int32_t c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = jb + u;
+            const int jc = j < j1 ? j : j1 - 1;       // uniform clamp keeps offsets[] in range
+            int64_t a = JD ? offsets[jc] + base : base + int64_t(jc) * BR;
+            // With BR >= 64 every slot below the wave maximum exists (it is padding at
+            // worst).  With BR == 32 the second block of the wave may be shorter: lanes past
+            // their own row read slot 0 instead, which always exists.
+            if (BR < kWave) a = jc < len ? a : 0;
+            v[u] = ld_stream(val_p + a);
+            c[u] = ld_stream(col_p + a);
+        }
+        T xv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = jb + u;
+            const T s = __builtin_fma(v[u], xv[u], acc);
+            acc = (j < len && j < j1) ? s : acc;
+        }
+    }
+    return acc;
+}
+
+template <class T, bool JD, int BR>
+__global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
+    int64_t n_rows, int64_t n_pad, int64_t n_groups, int64_t n_chunks, int32_t split_len,
+    const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ sched,
+    T *__restrict__ partials, int32_t *__restrict__ counters,
+    const T *__restrict__ x, T *__restrict__ y, uint32_t flags) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+
+    if (w < n_chunks) {
+        // ---- one work item of a long wave group
+        const int32_t g = sched[4 * w + 0], c = sched[4 * w + 1], nc = sched[4 * w + 2], first = sched[4 * w + 3];
+        const int64_t i = int64_t(g) * kWave + lane;
+        const int len = i < n_pad ? row_len[i] : 0;
+        const int m = wave_max(len);
+        const int j0 = c * split_len, j1 = min(j0 + split_len, m);
+        const T part = row_range_sum<T, JD, BR>(i, len, j0, j1, offsets, col_p, val_p, x);
+        partials[w * kWave + lane] = part;
+        __threadfence();                                    // publish the partial sums
+        int last = 0;
+        if (lane == 0) last = atomicAdd(&counters[first], 1) == nc - 1;
+        last = __shfl(last, 0);
+        if (last) {
+            __threadfence();                                // see every item's partials
+            const volatile T *pp = partials + int64_t(first) * kWave + lane;
+            T s = pp[0];
+            for (int q = 1; q < nc; ++q) s += pp[int64_t(q) * kWave];
+            if (i < n_rows) y[y_perm ? i : perm[i]] = s;
+            if (lane == 0) counters[first] = 0;             // ready for the next product
+        }
+        return;
+    }
+    const int64_t g = w - n_chunks;
+    if (g >= n_groups) return;
+    const int64_t i = g * kWave + lane;
+    const int len = i < n_pad ? row_len[i] : 0;
+    const int m = wave_max(len);
+    if (split_len > 0 && m > split_len) return;            // done by the work items above
+    const T acc = row_range_sum<T, JD, BR>(i, len, 0, m, offsets, col_p, val_p, x);
+    if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
+}
+
+__global__ void zero_ints_kernel(int32_t *p, int64_t n) {
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) p[k] = 0;
+}
+
+// ---- pJDS with k right-hand sides -----------------------------------------------------
+template <class T, bool JD, int BR, int TILE>
+__global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
+    int64_t n_rows, int64_t n_pad, int64_t n_groups, int32_t k,
+    const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+    const int32_t *__restrict__ perm, const T *__restrict__ X, T *__restrict__ Y, uint32_t flags) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t g = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (g >= n_groups) return;
+    const int v0 = blockIdx.y * TILE;
+    const int tv = min(TILE, k - v0);
+    const int64_t i = g * kWave + lane;
+    const int len = i < n_pad ? row_len[i] : 0;
+    const int m = wave_max(len);
+    const int64_t base = JD ? i : offsets[i / BR] + (i % BR);
+    T acc[TILE];
+#pragma unroll
+    for (int t = 0; t < TILE; ++t) acc[t] = T(0);
+    constexpr int U = TILE >= 4 ? 2 : 4;
+    for (int jb = 0; jb < m; jb += U) {
+        T v[U];
+        int32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = jb + u;
+            const int jc = j < m ? j : m - 1;
+            int64_t a = JD ? offsets[jc] + base : base + int64_t(jc) * BR;
+            if (BR < kWave) a = jc < len ? a : 0;
+            v[u] = ld_stream(val_p + a);
+            c[u] = ld_stream(col_p + a);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool on = jb + u < len && jb + u < m;
+            const T *xr = X + int64_t(c[u]) * k + v0;
+#pragma unroll
+            for (int t = 0; t < TILE; ++t) {
+                if (t < tv) {
+                    const T s = __builtin_fma(v[u], xr[t], acc[t]);
+                    acc[t] = on ? s : acc[t];
+                }
+            }
+        }
+    }
+    if (i < n_rows) {
+        T *yr = Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v0;
+#pragma unroll
+        for (int t = 0; t < TILE; ++t)
+            if (t < tv) yr[t] = acc[t];
+    }
+}
+
+// ---- ELLPACK-R, Listing 1 -------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kBlock) void ellr_spmv_kernel(
+    int64_t n_rows, int64_t n_pad, const int32_t *__restrict__ rowmax,
+    const int32_t *__restrict__ col_e, const T *__restrict__ val_e,
+    const T *__restrict__ x, T *__restrict__ y) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const int len = i < n_pad ? rowmax[i] : 0;
+    const int m = wave_max(len);
+    T acc = T(0);
+    for (int jb = 0; jb < m; jb += kUnroll) {
+        T v[kUnroll];
+        int32_t c[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = jb + u < m ? jb + u : m - 1;
+            const int64_t a = int64_t(j) * n_pad + (i < n_pad ? i : 0);
+            v[u] = ld_stream(val_e + a);
+            c[u] = ld_stream(col_e + a);
+        }
+        T xv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const T s = __builtin_fma(v[u], xv[u], acc);
+            acc = (jb + u < len) ? s : acc;
+        }
+    }
+    if (i < n_rows) y[i] = acc;
+}
+
+// ---- CSR --------------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kBlock) void csr_scalar_kernel(
+    int64_t n_rows, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n_rows) return;
+    T acc = T(0);
+    for (int64_t k = row_ptr[i], e = row_ptr[i + 1]; k < e; ++k)
+        acc = __builtin_fma(val[k], x[col[k]], acc);
+    y[i] = acc;
+}
+
+template <class T, int G>
+__global__ __launch_bounds__(kBlock) void csr_vector_kernel(
+    int64_t n_rows, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y) {
+    const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t i = t / G;
+    const int sub = int(t % G);
+    T acc = T(0);
+    if (i < n_rows)
+        for (int64_t k = row_ptr[i] + sub, e = row_ptr[i + 1]; k < e; k += G)
+            acc = __builtin_fma(val[k], x[col[k]], acc);
+    // butterfly: every lane of the group ends with the same, order-fixed sum
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (i < n_rows && sub == 0) y[i] = acc;
+}
+
+// ---- bandwidth probes ---------------------------------------------------------------------
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kBlock) void probe_read_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
+    double s = 0.0;
+    const int64_t n2 = n / 2;
+    const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
+    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += int64_t(gridDim.x) * kBlock) {
+        dbl2 v = __builtin_nontemporal_load(in2 + k);
+        s += v.x + v.y;
+    }
+    if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) s += in[n - 1];
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
+    const int64_t n2 = n / 2;
+    const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
+    dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
+    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += int64_t(gridDim.x) * kBlock)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(in2 + k), out2 + k);
+    if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) out[n - 1] = in[n - 1];
+}
+
+int launch_status(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PJDS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return PJDS_OK;
+}
+
+int64_t ws_partials_bytes(const pjds_info &in, int32_t dtype) {
+    const int64_t sz = dtype == PJDS_F64 ? 8 : 4;
+    return (in.n_chunks * kWave * sz + 255) / 256 * 256;
+}
+
+template <class T, bool JD, int BR>
+void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
+                 const void *vp, const int32_t *perm, const int32_t *sched, void *work,
+                 const void *x, void *y, uint32_t flags, hipStream_t s) {
+    const int64_t groups = ceil_div(in.n_pad, kWave);
+    const int64_t waves = in.n_chunks + groups;
+    const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)));
+    T *partials = static_cast<T *>(work);
+    int32_t *counters = work ? reinterpret_cast<int32_t *>(static_cast<char *>(work) + ws_partials_bytes(in, sizeof(T) == 8 ? PJDS_F64 : PJDS_F32)) : nullptr;
+    hipLaunchKernelGGL((pjds_spmv_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad,
+                       groups, in.n_chunks, in.split_len, rl, off, cp, static_cast<const T *>(vp),
+                       perm, sched, partials, counters, static_cast<const T *>(x),
+                       static_cast<T *>(y), flags);
+}
+
+template <class T, bool JD, int BR>
+void launch_spmmv(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
+                  const void *vp, const int32_t *perm, int32_t k, int32_t t, const void *X,
+                  void *Y, uint32_t flags, hipStream_t s) {
+    const int64_t groups = ceil_div(in.n_pad, kWave);
+    const dim3 grid(unsigned(ceil_div(groups, kWavesPerBlock)), unsigned(ceil_div(k, t)));
+#define PJDS_SPMMV_CASE(TT)                                                                           \
+    case TT:                                                                                          \
+        hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, TT>), grid, dim3(kBlock), 0, s, in.n_rows,  \
+                           in.n_pad, groups, k, rl, off, cp, static_cast<const T *>(vp), perm,        \
+                           static_cast<const T *>(X), static_cast<T *>(Y), flags);                    \
+        break;
+    switch (t) {
+        PJDS_SPMMV_CASE(1)
+        PJDS_SPMMV_CASE(2)
+        PJDS_SPMMV_CASE(4)
+        PJDS_SPMMV_CASE(8)
+    }
+#undef PJDS_SPMMV_CASE
+}
+
+// Dispatch on (dtype, layout, block height) to a compile-time instantiation.
+template <template <class, bool, int> class K, class... A>
+void dispatch(int32_t dtype, bool jd, int32_t br, A &&...a) {
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        if (jd) {
+            if (br == 32) K<T, true, 32>::run(a...);
+            else if (br == 64) K<T, true, 64>::run(a...);
+            else K<T, true, 128>::run(a...);
+        } else {
+            if (br == 32) K<T, false, 32>::run(a...);
+            else if (br == 64) K<T, false, 64>::run(a...);
+            else K<T, false, 128>::run(a...);
+        }
+    };
+    if (dtype == PJDS_F64) go(double{});
+    else go(float{});
+}
+
+template <class T, bool JD, int BR>
+struct SpmvK {
+    template <class... A>
+    static void run(A &&...a) { launch_pjds<T, JD, BR>(a...); }
+};
+template <class T, bool JD, int BR>
+struct SpmmvK {
+    template <class... A>
+    static void run(A &&...a) { launch_spmmv<T, JD, BR>(a...); }
+};
+
+int check_info(const pjds_info *info, int32_t dtype) {
+    if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
+    if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
+    const int32_t br = info->block_height;
+    if (br != 32 && br != 64 && br != 128) return fail(PJDS_ERR_ARG, "block_height %d", br);
+    if (info->n_rows < 0 || info->n_pad < info->n_rows || info->n_pad % br) return fail(PJDS_ERR_ARG, "inconsistent info");
+    return PJDS_OK;
+}
+
+}  // namespace
+}  // namespace pjds
+
+using namespace pjds;
+
+extern "C" {
+
+int pjds_workspace_size(const pjds_info *info, int32_t dtype, int64_t *bytes) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (!bytes) return fail(PJDS_ERR_ARG, "bytes is NULL");
+    *bytes = info->n_chunks ? ws_partials_bytes(*info, dtype) + (info->n_chunks * 4 + 255) / 256 * 256 : 0;
+    return PJDS_OK;
+}
+
+int pjds_workspace_init(const pjds_info *info, int32_t dtype, void *d_work, void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (!info->n_chunks) return PJDS_OK;
+    if (!d_work) return fail(PJDS_ERR_ARG, "d_work is NULL");
+    int32_t *counters = reinterpret_cast<int32_t *>(static_cast<char *>(d_work) + ws_partials_bytes(*info, dtype));
+    const int64_t n = info->n_chunks;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(unsigned(std::min<int64_t>(ceil_div(n, kBlock), 1024))), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), counters, n);
+    return launch_status("pjds_workspace_init");
+}
+
+int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+              const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+              const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x, void *d_y,
+              uint32_t flags, void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_NO_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
+    if (info->n_chunks && (!d_sched || !d_work)) return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
+    dispatch<SpmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
+                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, flags,
+                    static_cast<hipStream_t>(stream));
+    return launch_status("pjds_spmv");
+}
+
+int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+               const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+               int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
+               uint32_t flags, void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_NO_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (k < 1) return fail(PJDS_ERR_ARG, "k = %d", k);
+    const int32_t t = vectors_per_tile;
+    if (t != 1 && t != 2 && t != 4 && t != 8) return fail(PJDS_ERR_ARG, "vectors_per_tile %d: must be 1, 2, 4 or 8", t);
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_Y) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_X)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter Y)");
+    if (ceil_div(k, t) > 65535) return fail(PJDS_ERR_ARG, "too many vector tiles");
+    dispatch<SpmmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
+                     d_offsets, d_col_p, d_val_p, d_perm, k, t, d_X, d_Y, flags,
+                     static_cast<hipStream_t>(stream));
+    return launch_status("pjds_spmmv");
+}
+
+int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_col_e,
+              const void *d_val_e, int32_t dtype, const void *d_x, void *d_y, void *stream) {
+    if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
+    if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
+    if (info->n_pad % kWave || info->n_pad < info->n_rows) return fail(PJDS_ERR_ARG, "inconsistent ELLPACK-R info");
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_rowmax || !d_y || (info->nnz_stored && (!d_col_e || !d_val_e || !d_x))) return fail(PJDS_ERR_ARG, "NULL device array");
+    const dim3 grid(unsigned(ceil_div(info->n_pad, kBlock)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == PJDS_F64)
+        hipLaunchKernelGGL(ellr_spmv_kernel<double>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
+                           d_col_e, static_cast<const double *>(d_val_e), static_cast<const double *>(d_x), static_cast<double *>(d_y));
+    else
+        hipLaunchKernelGGL(ellr_spmv_kernel<float>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
+                           d_col_e, static_cast<const float *>(d_val_e), static_cast<const float *>(d_x), static_cast<float *>(d_y));
+    return launch_status("ellr_spmv");
+}
+
+int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int32_t *d_col,
+             const void *d_val, int32_t dtype, const void *d_x, void *d_y, int32_t variant, void *stream) {
+    if (n_rows < 0 || n_cols < 0) return fail(PJDS_ERR_ARG, "negative size");
+    if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
+    if (variant != 1 && variant != 4 && variant != 16 && variant != 64) return fail(PJDS_ERR_ARG, "variant %d: must be 1, 4, 16 or 64", variant);
+    if (n_rows == 0) return PJDS_OK;
+    if (!d_row_ptr || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t threads = n_rows * variant;
+    if (ceil_div(threads, kBlock) > INT32_MAX) return fail(PJDS_ERR_OVERFLOW, "grid too large");
+    const dim3 grid(unsigned(ceil_div(threads, kBlock)));
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        const T *v = static_cast<const T *>(d_val);
+        const T *x = static_cast<const T *>(d_x);
+        T *y = static_cast<T *>(d_y);
+        switch (variant) {
+            case 1: hipLaunchKernelGGL(csr_scalar_kernel<T>, grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            case 4: hipLaunchKernelGGL((csr_vector_kernel<T, 4>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            case 16: hipLaunchKernelGGL((csr_vector_kernel<T, 16>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            default: hipLaunchKernelGGL((csr_vector_kernel<T, 64>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+        }
+    };
+    if (dtype == PJDS_F64) go(double{});
+    else go(float{});
+    return launch_status("csr_spmv");
+}
+
+int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream) {
+    if ((mode != 0 && mode != 1) || n < 0 || !d_in || !d_out) return fail(PJDS_ERR_ARG, "bad probe arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid(unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n / 2, kBlock * 8), 1), 256 * 16)));
+    if (mode == 0) hipLaunchKernelGGL(probe_read_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    else hipLaunchKernelGGL(probe_copy_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    return launch_status("pjds_probe");
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+"""Device-resident sparse matrices built through the C interface.
+
+``PjdsMatrix.from_csr`` plans and converts on the host (pjds_plan / pjds_convert), then
+copies the arrays to the GPU once; ``spmv`` / ``spmmv`` launch the HIP kernels on the
+current (or given) stream.  ``EllrMatrix`` and ``CsrMatrix`` do the same for the two
+comparison formats.  Inputs are any object with ``n_rows, n_cols, row_ptr, col, val``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _to_dev(a: np.ndarray, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def _tdtype(np_dtype) -> torch.dtype:
+    return {np.dtype(np.float64): torch.float64, np.dtype(np.float32): torch.float32}[np.dtype(np_dtype)]
+
+
+class PjdsMatrix:
+    """A pJDS matrix on the GPU (Sect. 2.1 of the paper; see include/pjds.h)."""
+
+    def __init__(self):
+        self.info: L.pjds_info | None = None
+        self.host: dict = {}
+
+    @classmethod
+    def from_csr(cls, A, block_height: int = 64, sort_window: int = 0, layout: str = "jd",
+                 symmetric: bool = False, split_len: int = 0, device="cuda",
+                 keep_host: bool = False) -> "PjdsMatrix":
+        self = cls()
+        flags = (L.PJDS_LAYOUT_BLOCK if layout == "block" else L.PJDS_LAYOUT_JD) | (L.PJDS_SYMMETRIC if symmetric else 0)
+        row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(A.col, dtype=np.int32)
+        val = np.ascontiguousarray(A.val)
+        info = L.pjds_plan(A.n_rows, A.n_cols, row_ptr, block_height, sort_window, flags, split_len)
+        h = dict(
+            perm=np.empty(max(info.n_rows, 1), np.int32),
+            row_len=np.empty(max(info.n_pad, 1), np.int32),
+            offsets=np.empty(max(info.n_offsets, 1), np.int64),
+            col_p=np.empty(max(info.nnz_stored, 1), np.int32),
+            val_p=np.empty(max(info.nnz_stored, 1), val.dtype),
+            sched=np.empty(max(4 * info.n_chunks, 1), np.int32),
+        )
+        L.pjds_convert(info, row_ptr, col, val, h["perm"], h["row_len"], h["offsets"], h["col_p"],
+                       h["val_p"], h["sched"] if info.n_chunks else None)
+        self.info = info
+        self.dtype = _tdtype(val.dtype)
+        self.device = torch.device(device)
+        self.d = {k: _to_dev(v, self.device) for k, v in h.items()}
+        ws = L.pjds_workspace_size(info, self.dtype)
+        self.d["work"] = torch.empty(max(ws, 1), dtype=torch.uint8, device=self.device) if ws else None
+        if ws:
+            L.pjds_workspace_init(info, self.dtype, self.d["work"])
+        if keep_host:
+            self.host = {k: (v[:info.n_rows] if k == "perm" else v[:info.n_pad] if k == "row_len"
+                             else v[:info.n_offsets] if k == "offsets" else v[:4 * info.n_chunks] if k == "sched"
+                             else v[:info.nnz_stored]) for k, v in h.items()}
+        return self
+
+    @property
+    def n_rows(self) -> int:
+        return self.info.n_rows
+
+    @property
+    def n_cols(self) -> int:
+        return self.info.n_cols
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, y_permuted: bool = False,
+             xcd_remap: bool = True, stream=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
+        flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (0 if xcd_remap else L.PJDS_NO_XCD_REMAP)
+        d = self.d
+        L.pjds_spmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"],
+                    d["sched"] if self.info.n_chunks else None, d["work"], x, y, flags, stream)
+        return y
+
+    def spmmv(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int = 4,
+              y_permuted: bool = False, stream=None) -> torch.Tensor:
+        k = X.shape[1]
+        if Y is None:
+            Y = torch.empty((self.info.n_rows, k), dtype=self.dtype, device=self.device)
+        flags = L.PJDS_Y_PERMUTED if y_permuted else 0
+        d = self.d
+        L.pjds_spmmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], k,
+                     vectors_per_tile, X, Y, flags, stream)
+        return Y
+
+    def footprint_bytes(self) -> int:
+        """Device bytes of the format: values, column indices, row lengths, offsets, perm."""
+        i = self.info
+        vb = 8 if self.dtype == torch.float64 else 4
+        return i.nnz_stored * (vb + 4) + i.n_pad * 4 + i.n_offsets * 8 + i.n_rows * 4
+
+
+class EllrMatrix:
+    """An ELLPACK-R matrix on the GPU (Listing 1)."""
+
+    @classmethod
+    def plan(cls, A) -> L.pjds_info:
+        return L.ellr_plan(A.n_rows, A.n_cols, np.ascontiguousarray(A.row_ptr, dtype=np.int64))
+
+    @classmethod
+    def from_csr(cls, A, device="cuda", keep_host: bool = False) -> "EllrMatrix":
+        self = cls()
+        row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+        val = np.ascontiguousarray(A.val)
+        info = L.ellr_plan(A.n_rows, A.n_cols, row_ptr)
+        h = dict(rowmax=np.empty(max(info.n_pad, 1), np.int32),
+                 col_e=np.empty(max(info.nnz_stored, 1), np.int32),
+                 val_e=np.empty(max(info.nnz_stored, 1), val.dtype))
+        L.ellr_convert(info, row_ptr, np.ascontiguousarray(A.col, dtype=np.int32), val, h["rowmax"],
+                       h["col_e"], h["val_e"])
+        self.info = info
+        self.dtype = _tdtype(val.dtype)
+        self.device = torch.device(device)
+        self.d = {k: _to_dev(v, self.device) for k, v in h.items()}
+        self.host = {"rowmax": h["rowmax"][:info.n_pad], "col_e": h["col_e"][:info.nnz_stored],
+                     "val_e": h["val_e"][:info.nnz_stored]} if keep_host else {}
+        return self
+
+    def spmv(self, x, y=None, stream=None):
+        if y is None:
+            y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
+        L.ellr_spmv(self.info, self.d["rowmax"], self.d["col_e"], self.d["val_e"], x, y, stream)
+        return y
+
+    def footprint_bytes(self) -> int:
+        vb = 8 if self.dtype == torch.float64 else 4
+        return self.info.nnz_stored * (vb + 4) + self.info.n_pad * 4
+
+
+class CsrMatrix:
+    """The input CSR arrays on the GPU, for the CSR kernels."""
+
+    @classmethod
+    def from_csr(cls, A, device="cuda") -> "CsrMatrix":
+        self = cls()
+        self.n_rows, self.n_cols = A.n_rows, A.n_cols
+        self.dtype = _tdtype(np.asarray(A.val).dtype)
+        self.device = torch.device(device)
+        self.row_ptr = _to_dev(np.asarray(A.row_ptr, np.int64), self.device)
+        self.col = _to_dev(np.asarray(A.col, np.int32) if len(A.col) else np.zeros(1, np.int32), self.device)
+        self.val = _to_dev(np.asarray(A.val) if len(A.val) else np.zeros(1, np.asarray(A.val).dtype), self.device)
+        self.nnz = int(A.row_ptr[-1])
+        return self
+
+    def spmv(self, x, y=None, variant: int = 1, stream=None):
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=self.dtype, device=self.device)
+        L.csr_spmv(self.n_rows, self.n_cols, self.row_ptr, self.col, self.val, x, y, variant, stream)
+        return y
+
+    def footprint_bytes(self) -> int:
+        vb = 8 if self.dtype == torch.float64 else 4
+        return self.nnz * (vb + 4) + (self.n_rows + 1) * 8

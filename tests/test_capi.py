@@ -1,0 +1,146 @@
+"""The C interface as a library: it loads without a GPU, exports every function the header
+declares, and rejects bad input with a status code and a message, writing nothing."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_1112_5588_amd import _lib as L
+
+HEADER_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if fn.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", text, flags=re.M))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "pjds_spmv" in names and "pjds_convert" in names and "ellr_spmv" in names and "csr_spmv" in names
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert not set(names) - set(L.EXPORTED)
+
+
+def test_version_and_error_string():
+    assert "gfx950" in L.pjds_version()
+    with pytest.raises(L.PjdsError):
+        L.pjds_plan(4, 4, np.array([0, 1, 2, 3, 4], np.int64), block_height=48)
+    assert "block_height" in L.pjds_last_error()
+
+
+def rp(*v):
+    return np.array(v, dtype=np.int64)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((3, 3, rp(1, 1, 2, 3)), L.PJDS_ERR_INDEX),           # row_ptr[0] != 0
+    ((3, 3, rp(0, 2, 1, 3)), L.PJDS_ERR_INDEX),           # decreasing
+    ((-1, 3, rp(0)), L.PJDS_ERR_ARG),                      # negative size
+    ((1 << 31, 3, rp(0)), L.PJDS_ERR_OVERFLOW),            # rows beyond int32
+])
+def test_plan_rejects_bad_row_ptr(args, code):
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_plan(*args)
+    assert e.value.code == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(block_height=16), L.PJDS_ERR_ARG),
+    (dict(block_height=96), L.PJDS_ERR_ARG),
+    (dict(sort_window=100, flags=L.PJDS_LAYOUT_BLOCK), L.PJDS_ERR_ARG),   # not a multiple of 64
+    (dict(sort_window=128, flags=L.PJDS_LAYOUT_JD), L.PJDS_ERR_ARG),      # JD needs a global sort
+    (dict(flags=0x40), L.PJDS_ERR_ARG),
+    (dict(split_len=12), L.PJDS_ERR_ARG),
+])
+def test_plan_rejects_bad_options(kw, code):
+    A = synth.random_csr(1000, 50, 1)
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, **kw)
+    assert e.value.code == code
+
+
+def test_symmetric_needs_square():
+    A = synth.random_csr(100, 50, 1)
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, flags=L.PJDS_SYMMETRIC)
+    assert e.value.code == L.PJDS_ERR_ARG
+
+
+def test_convert_rejects_column_out_of_range_without_writing():
+    A = synth.random_csr(200, 40, 3, max_len=10, empty_frac=0.0)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr)
+    bad = A.col.copy()
+    bad[len(bad) // 2] = 40
+    outs = [np.full(info.n_rows, -9, np.int32), np.full(info.n_pad, -9, np.int32),
+            np.full(info.n_offsets, -9, np.int64), np.full(info.nnz_stored, -9, np.int32),
+            np.full(info.nnz_stored, -9.0)]
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_convert(info, A.row_ptr, bad, A.val, *outs)
+    assert e.value.code == L.PJDS_ERR_INDEX
+    assert "column index 40" in L.pjds_last_error()
+    for o in outs:
+        assert np.all(o == -9)
+    bad[len(bad) // 2] = -1
+    with pytest.raises(L.PjdsError):
+        L.pjds_convert(info, A.row_ptr, bad, A.val, *outs)
+
+
+def test_convert_rejects_mismatched_info():
+    A = synth.random_csr(200, 40, 3)
+    B = synth.random_csr(200, 40, 4)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr)
+    outs = [np.empty(info.n_rows, np.int32), np.empty(info.n_pad, np.int32),
+            np.empty(info.n_offsets, np.int64), np.empty(max(info.nnz_stored, 1), np.int32),
+            np.empty(max(info.nnz_stored, 1))]
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_convert(info, B.row_ptr, B.col, B.val, *outs)
+    assert e.value.code == L.PJDS_ERR_ARG
+
+
+def test_convert_requires_schedule_for_long_rows():
+    A = synth.powerlaw(1 << 12, seed=3, l_max=1024)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, split_len=64)
+    assert info.n_chunks > 0
+    outs = [np.empty(info.n_rows, np.int32), np.empty(info.n_pad, np.int32),
+            np.empty(info.n_offsets, np.int64), np.empty(info.nnz_stored, np.int32),
+            np.empty(info.nnz_stored)]
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_convert(info, A.row_ptr, A.col, A.val, *outs, None)
+    assert e.value.code == L.PJDS_ERR_ARG
+
+
+def test_ellr_plan_reports_size_of_skewed_matrix():
+    # The power-law matrix (N = 2^23, longest row 4096) would need n_pad * 4096 entries in
+    # ELLPACK-R: the planner reports it so the caller can refuse to allocate.
+    n = 1 << 23
+    lens = np.full(n, 12, np.int64)
+    lens[5] = 4096
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    info = L.ellr_plan(n, n, row_ptr)
+    assert info.nnz_stored == n * 4096
+    assert info.nnz_stored * 12 > 288 * 2 ** 30        # over an MI355X's HBM in FP64
+
+
+def test_device_entry_points_validate_before_touching_the_gpu():
+    A = synth.random_csr(100, 100, 1)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr)
+    lib = L.lib()
+    # NULL arrays / bad dtype / bad flags are refused on the host
+    assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 7, None, None, 0, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0x100, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 3, None, None, 0, None) == L.PJDS_ERR_ARG
+    assert lib.csr_spmv(10, 10, None, None, None, 0, None, None, 5, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_probe(3, None, None, 10, None) == L.PJDS_ERR_ARG

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP kernels (through the C interface) against the CPU oracle on the same
+seeded inputs.  FP64 within 1e-12 relative L2, FP32 within 1e-5; integer-valued data and
+index arrays bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1112_5588_amd import CsrMatrix, EllrMatrix, PjdsMatrix
+from paper_1112_5588_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def check_pjds(A, x, b_r=64, layout="jd", window=0, y_permuted=False, symmetric=False,
+               split_len=0, tol=None):
+    M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, sort_window=window,
+                            symmetric=symmetric, split_len=split_len, keep_host=True)
+    perm = M.host["perm"]
+    xin = x[perm] if symmetric else x
+    y = host(M.spmv(dev(xin, M.dtype), y_permuted=y_permuted))
+    # symmetric renumbering changes the basis of x only: slot i of the product is still
+    # original row perm[i], written there (y_permuted) or scattered back to row perm[i]
+    ref = oracle.csr_spmv(A, x)
+    if y_permuted:
+        ref = ref[perm]
+    err = oracle.rel_l2(y, ref)
+    assert err <= (tol if tol is not None else TOL[M.dtype]), err
+    return M, y
+
+
+# ------------------------------------------------------------------ config 1, exact cases
+
+@pytest.mark.parametrize("layout", ["jd", "block"])
+@pytest.mark.parametrize("y_permuted", [False, True])
+def test_laplacian_times_ones_is_exact(layout, y_permuted):
+    A = synth.laplacian_2d(128)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout=layout, keep_host=True)
+    y = host(M.spmv(dev(np.ones(A.n_cols)), y_permuted=y_permuted))
+    r, c = np.divmod(np.arange(A.n_rows), 128)
+    expect = ((r == 0).astype(float) + (r == 127) + (c == 0) + (c == 127))
+    if y_permuted:
+        expect = expect[M.host["perm"]]
+    assert np.array_equal(y, expect)
+
+
+@pytest.mark.parametrize("b_r", [32, 64, 128])
+def test_integer_data_bit_exact(b_r):
+    # small integers: every sum is exact in any order, so the GPU must reproduce it bit for bit
+    A = synth.random_csr(5000, 3000, 8, max_len=30, integer=True)
+    x = synth.dense_x(3000, 8, integer=True)
+    M = PjdsMatrix.from_csr(A, block_height=b_r)
+    assert np.array_equal(host(M.spmv(dev(x))), oracle.csr_spmv(A, x))
+
+
+def test_config1_random_x():
+    A = synth.laplacian_2d(128)
+    x = synth.dense_x(A.n_cols, 1)
+    for layout in ("jd", "block"):
+        for yp in (False, True):
+            check_pjds(A, x, layout=layout, y_permuted=yp)
+
+
+# ------------------------------------------------------------------ format options
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("b_r", [32, 64, 128])
+@pytest.mark.parametrize("layout", ["jd", "block"])
+@pytest.mark.parametrize("y_permuted", [False, True])
+def test_random_matrix_tiles_and_ragged_tail(dtype, b_r, layout, y_permuted):
+    # 9501 rows: 37 workgroups of 256 rows plus a ragged tail of 29 rows
+    A = synth.random_csr(9501, 7000, 21, max_len=45, empty_frac=0.1).astype(dtype)
+    x = synth.dense_x(7000, 21)
+    if dtype == np.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    check_pjds(A, x, b_r=b_r, layout=layout, y_permuted=y_permuted)
+
+
+@pytest.mark.parametrize("window", [64, 1024, 4096])
+@pytest.mark.parametrize("b_r", [32, 64, 128])
+def test_sort_windows(window, b_r):
+    if window % b_r:
+        pytest.skip("window must hold whole blocks")
+    A = synth.powerlaw(20000, seed=5, l_max=300)
+    check_pjds(A, synth.dense_x(20000, 5), b_r=b_r, layout="block", window=window)
+
+
+@pytest.mark.parametrize("y_permuted", [False, True])
+def test_symmetric_permuted_basis(y_permuted):
+    A = synth.hh_like(50000, seed=9)
+    check_pjds(A, synth.dense_x(50000, 9), symmetric=True, y_permuted=y_permuted)
+
+
+@pytest.mark.parametrize("split_len", [-1, 64, 128, 256])
+@pytest.mark.parametrize("b_r", [32, 64, 128])
+def test_long_rows_split(split_len, b_r):
+    A = synth.powerlaw(1 << 16, seed=6, l_max=4096)
+    x = synth.dense_x(A.n_cols, 6)
+    M, y1 = check_pjds(A, x, b_r=b_r, split_len=split_len)
+    if split_len > 0:
+        assert M.info.n_chunks > 0
+    # bitwise reproducible run to run, and independent of the XCD renumbering
+    xd = dev(x)
+    for remap in (True, False, True):
+        assert np.array_equal(host(M.spmv(xd, xcd_remap=remap)), y1)
+
+
+def test_padding_never_enters_the_sum():
+    # column 0 is never referenced; padding slots point at column 0 -> x[0] = NaN must not leak
+    A = synth.random_csr(3000, 2000, 4, max_len=40)
+    A = synth.CSR(A.n_rows, A.n_cols + 1, A.row_ptr, A.col + 1, A.val)
+    x = synth.dense_x(A.n_cols, 4)
+    x[0] = np.nan
+    for b_r in (32, 64, 128):
+        M = PjdsMatrix.from_csr(A, block_height=b_r)
+        assert M.info.nnz_stored > A.nnz
+        y = host(M.spmv(dev(x)))
+        assert np.all(np.isfinite(y))
+        assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-12
+
+
+def test_empty_inputs():
+    Z = synth.CSR(1000, 500, np.zeros(1001, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    M = PjdsMatrix.from_csr(Z)
+    y = torch.full((1000,), 7.0, dtype=torch.float64, device="cuda")
+    M.spmv(dev(np.ones(500)), y)
+    assert np.array_equal(host(y), np.zeros(1000))
+    E = synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert PjdsMatrix.from_csr(E).spmv(torch.zeros(0, dtype=torch.float64, device="cuda")).numel() == 0
+
+
+# ------------------------------------------------------------------ comparison formats
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_ellr_parity(dtype):
+    for A in (synth.laplacian_2d(128), synth.random_csr(9501, 7000, 3, max_len=45)):
+        A = A.astype(dtype)
+        x = synth.dense_x(A.n_cols, 3)
+        if dtype == np.float32:
+            x = x.astype(np.float32).astype(np.float64)
+        E = EllrMatrix.from_csr(A)
+        y = host(E.spmv(dev(x, E.dtype)))
+        assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= TOL[E.dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("variant", [1, 4, 16, 64])
+def test_csr_parity(dtype, variant):
+    A = synth.random_csr(9501, 7000, 13, max_len=45).astype(dtype)
+    x = synth.dense_x(7000, 13)
+    if dtype == np.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    C = CsrMatrix.from_csr(A)
+    y1 = host(C.spmv(dev(x, C.dtype), variant=variant))
+    assert oracle.rel_l2(y1, oracle.csr_spmv(A, x)) <= TOL[C.dtype]
+    assert np.array_equal(host(C.spmv(dev(x, C.dtype), variant=variant)), y1)
+
+
+# ------------------------------------------------------------------ many right-hand sides
+
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 32])
+@pytest.mark.parametrize("t", [1, 2, 4, 8])
+def test_spmmv_config1(k, t):
+    A = synth.laplacian_2d(128)
+    X = synth.dense_x(A.n_cols, 40, k=k).reshape(A.n_cols, k)
+    M = PjdsMatrix.from_csr(A)
+    Y = host(M.spmmv(dev(X), vectors_per_tile=t))
+    ref = oracle.csr_spmmv(A, X)
+    assert oracle.rel_l2(Y, ref) <= 1e-12
+    if k == 1:
+        assert np.array_equal(Y[:, 0], host(M.spmv(dev(X[:, 0]))))
+
+
+@pytest.mark.parametrize("b_r,layout", [(32, "jd"), (64, "block"), (128, "jd")])
+def test_spmmv_random(b_r, layout):
+    A = synth.random_csr(9501, 7000, 17, max_len=45)
+    X = synth.dense_x(7000, 41, k=5).reshape(7000, 5)
+    M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, keep_host=True)
+    for yp in (False, True):
+        Y = host(M.spmmv(dev(X), vectors_per_tile=4, y_permuted=yp))
+        ref = oracle.csr_spmmv(A, X)
+        if yp:
+            ref = ref[M.host["perm"]]
+        assert oracle.rel_l2(Y, ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+@pytest.fixture(scope="module")
+def hh_full():
+    return synth.hh_like(1 << 22, seed=2)
+
+
+def sampled_rows(A, rows):
+    lens = np.diff(A.row_ptr)[rows]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    idx = np.concatenate([np.arange(A.row_ptr[r], A.row_ptr[r + 1]) for r in rows])
+    return synth.CSR(len(rows), A.n_cols, rp, A.col[idx], A.val[idx])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_hh_like_full_size_sampled(hh_full, dtype):
+    A = hh_full.astype(dtype) if dtype == np.float32 else hh_full
+    x = synth.dense_x(A.n_cols, 2)
+    if dtype == np.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    M = PjdsMatrix.from_csr(A, block_height=64, keep_host=True)
+    assert M.info.max_row_len <= 21
+    y = host(M.spmv(dev(x, M.dtype), y_permuted=True))
+    rows = np.unique(np.concatenate([np.arange(64), np.arange(A.n_rows - 64, A.n_rows),
+                                     (synth.uniform01(77, 1, 4096) * A.n_rows).astype(np.int64)]))
+    # permuted slot i holds original row perm[i]
+    inv = np.empty_like(M.host["perm"])
+    inv[M.host["perm"]] = np.arange(A.n_rows, dtype=np.int32)
+    ref = oracle.csr_spmv(sampled_rows(A, rows), x)
+    assert oracle.rel_l2(y[inv[rows]], ref) <= TOL[M.dtype]
+    # footprint: pJDS stores fewer entries than ELLPACK-R would
+    E_info = EllrMatrix.plan(A)
+    assert M.info.nnz_stored < E_info.nnz_stored
+
+
+def test_powerlaw_full_size_sampled():
+    A = synth.powerlaw(1 << 23, seed=3)
+    x = synth.dense_x(A.n_cols, 3)
+    M = PjdsMatrix.from_csr(A, block_height=64, split_len=128, keep_host=True)
+    assert M.info.max_row_len == 4096 and M.info.n_chunks > 0
+    y = host(M.spmv(dev(x)))
+    rows = np.unique(np.concatenate([M.host["perm"][:2048],          # the longest rows (split)
+                                     (synth.uniform01(78, 1, 4096) * A.n_rows).astype(np.int64)]))
+    ref = oracle.csr_spmv(sampled_rows(A, rows), x)
+    assert oracle.rel_l2(y[rows], ref) <= 1e-12
+    assert np.array_equal(host(M.spmv(dev(x))), y)

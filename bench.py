@@ -100,6 +100,41 @@ def cpu_baseline(A, x, budget_s: float = 12.0):
     return y, dt, reps
 
 
+def batch_leg(torch) -> dict:
+    """512 uneven matrices (rows log-uniform in [1e3, 5e5], 3..60 entries per row, columns
+    within +-4096 of the diagonal), FP64: one persistent launch in a HIP graph vs one launch
+    per member captured in a graph vs one launch per member issued directly."""
+    import synth
+    from synth import torchgen
+    from paper_1112_5588_amd import PjdsBatch, PjdsMatrix, _lib
+    log("batch: generating and converting 512 matrices")
+    t0 = time.perf_counter()
+    sizes = synth.uneven_batch_sizes(512)
+    mats, xs, ys = [], [], []
+    for m, n in enumerate(sizes):
+        rp, col, val = torchgen.banded_stratified(int(n), 1000 + m, device="cuda")
+        mats.append(PjdsMatrix.from_arrays(int(n), int(n), rp, col, val, split_len=-1))
+        xs.append(torchgen.dense_x(int(n), 1000 + m, device="cuda"))
+        ys.append(torch.empty(int(n), dtype=torch.float64, device="cuda"))
+        del rp, col, val
+    t_setup = time.perf_counter() - t0
+    nnz = sum(M.info.nnz for M in mats)
+    rows = int(sizes.sum())
+    b_alg = 12 * nnz + 16 * rows
+    out = {"workload": "512 matrices, rows log-uniform in [1e3, 5e5], 3..60 entries per row within +-4096 of the diagonal, U[-1,1) FP64, seeds 1000+m",
+           "rows": rows, "nnz": nnz, "setup_s": round(t_setup, 1)}
+    log(f"batch: {rows} rows, {nnz} non-zeros, setup {t_setup:.1f}s; timing")
+    for name, mode in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT), ("per_member_graph", _lib.PJDS_BATCH_GRAPH),
+                       ("direct_launches", _lib.PJDS_BATCH_DIRECT)):
+        B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True)
+        ms = time_launches(B.launch, 10, 2)
+        out[name] = {"ms": round(ms, 4), "gflops": round(2 * nnz / ms / 1e6, 1), "GBps_alg": round(b_alg / ms / 1e6, 1)}
+        if mode == _lib.PJDS_BATCH_PERSISTENT:
+            out[name]["tiles"], out[name]["grid"] = B.info()
+        B.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -111,8 +146,11 @@ def main() -> int:
     ap.add_argument("--layout", default="jd", choices=["jd", "block"])
     ap.add_argument("--mode", default="y_permuted", choices=["y_permuted", "scatter", "symmetric"])
     ap.add_argument("--split-len", type=int, default=0)
+    ap.add_argument("--sort-window", type=int, default=0, help="0 = global sort")
+    ap.add_argument("--xcd-remap", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip comparison legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-matrix batch leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,8 +181,8 @@ def main() -> int:
     log(f"N={n} nnz={nnz} generated in {t_gen:.1f}s; converting")
     t0 = time.perf_counter()
     M = PjdsMatrix.from_csr(A, block_height=args.block_height, layout=args.layout,
-                            symmetric=args.mode == "symmetric", split_len=args.split_len,
-                            keep_host=args.mode == "symmetric")
+                            sort_window=args.sort_window, symmetric=args.mode == "symmetric",
+                            split_len=args.split_len, keep_host=args.mode == "symmetric")
     t_conv = time.perf_counter() - t0
     perm = M.d["perm"]
     x_dev = torch.from_numpy(x_np).to("cuda", tdt)
@@ -154,7 +192,7 @@ def main() -> int:
     y_perm = args.mode in ("y_permuted", "symmetric")
 
     def step():
-        M.spmv(x_dev, y_dev, y_permuted=y_perm)
+        M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
 
     log("timing")
     ms = time_launches(step, args.steps, args.warmup)
@@ -181,7 +219,7 @@ def main() -> int:
         import oracle
         out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
 
-    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_{args.mode}")
+    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_{args.mode}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",
         "value": round(gbs, 2),
@@ -197,6 +235,7 @@ def main() -> int:
         "data": "synthetic (seeded generator standing in for the paper's Holstein-Hubbard matrix)",
         "config": {"workload": desc, "n_rows": n, "nnz": nnz, "block_height": args.block_height,
                    "layout": args.layout, "mode": args.mode, "nnz_stored": M.info.nnz_stored,
+                   "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap,
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -210,19 +249,21 @@ def main() -> int:
     }
     result.update(out)
 
+    # achievable ceiling: read-only and copy probes over 2 GiB (the copy kernel of known
+    # size also calibrates the byte counters of a profiling run)
+    nprobe = 1 << 28
+    a = torch.empty(nprobe, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty(nprobe, dtype=torch.float64, device="cuda")
+    r = torch.empty(4096, dtype=torch.float64, device="cuda")
+    ms_r = time_launches(lambda: _lib.pjds_probe(0, a, r, nprobe), 10, 2)
+    ms_c = time_launches(lambda: _lib.pjds_probe(1, a, b, nprobe), 10, 2)
+    result["hbm_probe"] = {"bytes_read": 8 * nprobe, "read_GBps": round(8 * nprobe / ms_r / 1e6, 1),
+                           "copy_bytes": 16 * nprobe, "copy_GBps": round(16 * nprobe / ms_c / 1e6, 1)}
+    result["pct_of_probe_read"] = round(100 * gbs / result["hbm_probe"]["read_GBps"], 2)
+    del a, b, r
+
     if not args.no_extra:
         extra = {}
-        # achievable ceiling: read-only and copy probes over 2 GiB
-        nprobe = 1 << 28
-        a = torch.empty(nprobe, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty(nprobe, dtype=torch.float64, device="cuda")
-        r = torch.empty(4096, dtype=torch.float64, device="cuda")
-        ms_r = time_launches(lambda: _lib.pjds_probe(0, a, r, nprobe), 20, 3)
-        ms_c = time_launches(lambda: _lib.pjds_probe(1, a, b, nprobe), 20, 3)
-        extra["hbm_probe"] = {"read_GBps": round(8 * nprobe / ms_r / 1e6, 1),
-                              "copy_GBps": round(16 * nprobe / ms_c / 1e6, 1)}
-        del a, b
-        result["pct_of_probe_read"] = round(100 * gbs / extra["hbm_probe"]["read_GBps"], 2)
         # same matrix in the comparison formats
         log("ELLPACK-R and CSR legs")
         info_e = EllrMatrix.plan(A)
@@ -247,9 +288,9 @@ def main() -> int:
         del C
         # scatter-y and XCD-renumbering variants of the headline kernel
         ms_s = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=False), 50, 5)
-        ms_nr = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=False), 50, 5)
+        ms_nr = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=True), 50, 5)
         extra["pjds_scatter_y"] = {"ms": round(ms_s, 5)}
-        extra["pjds_no_xcd_remap"] = {"ms": round(ms_nr, 5)}
+        extra["pjds_xcd_remap"] = {"ms": round(ms_nr, 5)}
         # many right-hand sides on the same matrix: effective GFLOP/s vs plain single-vector
         spmmv = {}
         for k, t in ((4, 4), (8, 8)):
@@ -260,6 +301,10 @@ def main() -> int:
             del X, Y
         extra["spmmv"] = spmmv
         result["extra"] = extra
+        del M, x_dev, y_dev
+        torch.cuda.empty_cache()
+        if not args.no_batch:
+            result["batch"] = batch_leg(torch)
 
     print(json.dumps(result), flush=True)
     return 0

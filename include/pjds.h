@@ -58,8 +58,8 @@ extern "C" {
 /* Product flags (pjds_spmv, pjds_spmmv). */
 #define PJDS_Y_PERMUTED    0x4u  /* write y in the permuted row basis: y[i] = (A x)[perm[i]],
                                     coalesced; default scatters y to the original row order       */
-#define PJDS_NO_XCD_REMAP  0x8u  /* keep the hardware's round-robin block-to-XCD order instead of
-                                    giving each XCD a contiguous range of row blocks               */
+#define PJDS_XCD_REMAP     0x8u  /* renumber workgroups so each of the 8 XCDs processes one
+                                    contiguous range of row blocks (default: hardware round robin) */
 
 /* ---- pJDS -------------------------------------------------------------------------- */
 /*
@@ -154,15 +154,61 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               uint32_t flags, void *stream);
 
 /*
- * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v].
- * Each work item loads a matrix entry once and applies it to `vectors_per_tile` (1, 2, 4
- * or 8) consecutive right-hand sides, so the matrix is streamed ceil(k / t) times.
- * Arguments as pjds_spmv; k >= 1.  Long rows are not split here (d_sched unused).
+ * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v]
+ * (Y in the permuted row order with PJDS_Y_PERMUTED).  t = vectors_per_tile (1, 2, 4, 8,
+ * 16 or 32) consecutive lanes share one row, each applying the row's entries to one of t
+ * consecutive right-hand sides; a matrix entry is loaded once per tile of t vectors, so
+ * the matrix is streamed ceil(k / t) times and each gather reads t contiguous X values.
+ * Arguments as pjds_spmv; k >= 1; long rows are not split (no workspace needed).
  */
 int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
                int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
                uint32_t flags, void *stream);
+
+/* ---- many matrices in one call ------------------------------------------------------ */
+/*
+ * A batch computes y_m = A_m x_m for every member m (each member a pJDS matrix of the same
+ * block height and layout, any sizes).  Modes:
+ *   PJDS_BATCH_PERSISTENT  one persistent kernel: the members' rows are cut into tiles of
+ *                          `groups_per_tile` wave groups (64 sorted rows each; <= 0 -> 8),
+ *                          ordered by estimated work, longest first; each wave pulls tiles
+ *                          from one device counter until none is left.  A fill kernel resets
+ *                          the counter first.  Both are captured once in a HIP graph.
+ *   PJDS_BATCH_GRAPH       one pjds_spmv launch per member, captured in a HIP graph.
+ *   PJDS_BATCH_DIRECT      one pjds_spmv launch per member, issued on every launch call.
+ * Rows are never split into work items here, so members need no workspace.
+ * Ownership: the handle copies the pjds_info structs but keeps the device pointers; the
+ * caller keeps those buffers alive until pjds_batch_destroy.  The handle owns its device
+ * tables and graph.  Launches of one handle must not overlap (they share the tile
+ * counter); different handles are independent.
+ */
+#define PJDS_BATCH_PERSISTENT 0
+#define PJDS_BATCH_GRAPH      1
+#define PJDS_BATCH_DIRECT     2
+
+typedef struct pjds_batch_member {
+    const pjds_info *info;       /* host: the member's plan                                */
+    const int32_t *d_row_len;    /* device arrays of the member, as for pjds_spmv          */
+    const int64_t *d_offsets;
+    const int32_t *d_col_p;
+    const void    *d_val_p;
+    const int32_t *d_perm;       /* may be NULL with PJDS_Y_PERMUTED                        */
+    const void    *d_x;          /* device, [n_cols] dtype                                 */
+    void          *d_y;          /* device, [n_rows] dtype, written                         */
+} pjds_batch_member;
+
+typedef struct pjds_batch pjds_batch;
+
+/* flags: 0 or PJDS_Y_PERMUTED.  Errors: ERR_ARG (inconsistent members), ERR_HIP, ERR_NOMEM. */
+int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
+                      uint32_t flags, int32_t mode, int32_t groups_per_tile, pjds_batch **out);
+/* Enqueue one evaluation of the whole batch on `stream` (asynchronous). */
+int pjds_batch_launch(pjds_batch *batch, void *stream);
+/* Tile count and persistent grid size (workgroups) of a handle; either pointer may be NULL. */
+int pjds_batch_info(const pjds_batch *batch, int32_t *n_tiles, int32_t *grid);
+/* Free the handle, its device tables and graph (synchronise first if launches may still run). */
+int pjds_batch_destroy(pjds_batch *batch);
 
 /* ---- ELLPACK-R (Sect. 2.1, Listing 1) ---------------------------------------------- */
 /*

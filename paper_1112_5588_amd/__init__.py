@@ -8,6 +8,6 @@ arguments (``_lib``) and keeps device arrays (``matrix``).
 """
 from . import _lib
 from ._lib import PjdsError
-from .matrix import CsrMatrix, EllrMatrix, PjdsMatrix
+from .matrix import CsrMatrix, EllrMatrix, PjdsBatch, PjdsMatrix
 
-__all__ = ["PjdsMatrix", "EllrMatrix", "CsrMatrix", "PjdsError", "_lib"]
+__all__ = ["PjdsMatrix", "PjdsBatch", "EllrMatrix", "CsrMatrix", "PjdsError", "_lib"]

@@ -30,7 +30,7 @@ PJDS_LAYOUT_JD = 0x0
 PJDS_LAYOUT_BLOCK = 0x1
 PJDS_SYMMETRIC = 0x2
 PJDS_Y_PERMUTED = 0x4
-PJDS_NO_XCD_REMAP = 0x8
+PJDS_XCD_REMAP = 0x8
 
 
 class PjdsError(RuntimeError):
@@ -53,6 +53,18 @@ class pjds_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+PJDS_BATCH_PERSISTENT = 0
+PJDS_BATCH_GRAPH = 1
+PJDS_BATCH_DIRECT = 2
+
+
+class pjds_batch_member(ctypes.Structure):
+    _fields_ = [("info", ctypes.POINTER(pjds_info)), ("d_row_len", ctypes.c_void_p),
+                ("d_offsets", ctypes.c_void_p), ("d_col_p", ctypes.c_void_p),
+                ("d_val_p", ctypes.c_void_p), ("d_perm", ctypes.c_void_p),
+                ("d_x", ctypes.c_void_p), ("d_y", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -73,6 +85,10 @@ _SIGS = {
     "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "csr_spmv": [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp],
     "pjds_probe": [_i32, _vp, _vp, _i64, _vp],
+    "pjds_batch_create": [_i32, ctypes.POINTER(pjds_batch_member), _i32, _u32, _i32, _i32, ctypes.POINTER(_vp)],
+    "pjds_batch_launch": [_vp, _vp],
+    "pjds_batch_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "pjds_batch_destroy": [_vp],
     "pjds_last_error": [],
     "pjds_version": [],
 }
@@ -222,3 +238,31 @@ def csr_spmv(n_rows: int, n_cols: int, d_row_ptr, d_col, d_val, d_x, d_y, varian
 
 def pjds_probe(mode: int, d_in, d_out, n: int, stream=None) -> None:
     _check(lib().pjds_probe(mode, _dev(d_in), _dev(d_out), n, _stream(stream)), "pjds_probe")
+
+
+def pjds_batch_create(members: list, dtype, flags: int = 0, mode: int = PJDS_BATCH_PERSISTENT,
+                      groups_per_tile: int = 0) -> int:
+    """members: list of (info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y).
+    Returns the opaque handle (an integer address)."""
+    arr = (pjds_batch_member * len(members))()
+    for k, (info, rl, off, cp, vp, perm, x, y) in enumerate(members):
+        arr[k] = pjds_batch_member(ctypes.pointer(info), _dev(rl), _dev(off), _dev(cp), _dev(vp),
+                                   _dev(perm), _dev(x), _dev(y))
+    h = _vp()
+    _check(lib().pjds_batch_create(len(members), arr, _dtype_code(dtype), flags, mode,
+                                   groups_per_tile, ctypes.byref(h)), "pjds_batch_create")
+    return h.value
+
+
+def pjds_batch_launch(handle: int, stream=None) -> None:
+    _check(lib().pjds_batch_launch(handle, _stream(stream)), "pjds_batch_launch")
+
+
+def pjds_batch_info(handle: int) -> tuple[int, int]:
+    t, g = _i32(0), _i32(0)
+    _check(lib().pjds_batch_info(handle, ctypes.byref(t), ctypes.byref(g)), "pjds_batch_info")
+    return t.value, g.value
+
+
+def pjds_batch_destroy(handle: int) -> None:
+    _check(lib().pjds_batch_destroy(handle), "pjds_batch_destroy")

@@ -1,0 +1,324 @@
+// Many pJDS products at once: y_m = A_m x_m for a batch of matrices of very different sizes.
+//
+// Three execution modes share one handle:
+//  * PJDS_BATCH_PERSISTENT: a single launch of a persistent kernel.  The rows of all members
+//    are cut into tiles of up to `groups_per_tile` wave groups (64 sorted rows each); the
+//    tiles are ordered by estimated work, longest first, and every wave pulls the next tile
+//    from one device counter until the table is exhausted (every wave then exits).  A small
+//    fill kernel resets the counter in front of it.  Both kernels are captured once in a
+//    HIP graph; a launch replays it.
+//  * PJDS_BATCH_GRAPH: one pjds_spmv launch per member, captured in a HIP graph.
+//  * PJDS_BATCH_DIRECT: one pjds_spmv launch per member, issued on the stream each time.
+// Rows are never split here (no long-row workspace); results equal pjds_spmv's bit for bit
+// when the member was planned without long-row splitting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+namespace pjds {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+#ifndef PJDS_UNROLL
+#define PJDS_UNROLL 8
+#endif
+constexpr int kUnroll = PJDS_UNROLL;
+
+struct Member {                    // device-side descriptor of one batch member
+    const int32_t *row_len;
+    const int64_t *offsets;
+    const int32_t *col_p;
+    const void *val_p;
+    const int32_t *perm;
+    const void *x;
+    void *y;
+    int64_t n_rows, n_pad;
+};
+
+struct Tile {                      // wave groups [g0, g1) of member m
+    int32_t m, g0, g1, pad;
+};
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+
+template <int U, class T, bool JD, int BR>
+__device__ __forceinline__ void steps(T &acc, int jb, int len, int64_t base, int64_t base_lead,
+                                      const int64_t *__restrict__ off, const int32_t *__restrict__ col_p,
+                                      const T *__restrict__ val_p, const T *__restrict__ x) {
+    T v[U];
+    int32_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = jb + u;
+        const int64_t b = j < len ? base : base_lead;   // lead row: an entry at every such j
+        const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
+        v[u] = ld_stream(val_p + a);
+        c[u] = ld_stream(col_p + a);
+    }
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const T s = __builtin_fma(v[u], xv[u], acc);
+        acc = jb + u < len ? s : acc;
+    }
+}
+
+// One wave group of one member: Listing 2 over 64 sorted rows, same arithmetic order as
+// pjds_spmv (entries in stored order, one FMA each).
+template <class T, bool JD, int BR>
+__device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_perm) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t i = g * kWave + lane;
+    const int len = i < M.n_pad ? M.row_len[i] : 0;
+    const int m = wave_max(len);
+    T acc = T(0);
+    if (m > 0) {
+        const int64_t i_lead = i - lane + __builtin_ctzll(__ballot(len == m));
+        const int64_t base = JD ? i : M.offsets[i / BR] + (i % BR);
+        const int64_t base_lead = JD ? i_lead : M.offsets[i_lead / BR] + (i_lead % BR);
+        const T *val_p = static_cast<const T *>(M.val_p);
+        const T *x = static_cast<const T *>(M.x);
+        int jb = 0;
+        for (; jb + kUnroll <= m; jb += kUnroll) steps<kUnroll, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        if (kUnroll > 4 && jb + 4 <= m) { steps<4, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x); jb += 4; }
+        if (kUnroll > 2 && jb + 2 <= m) { steps<2, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x); jb += 2; }
+        if (jb < m) steps<1, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+    }
+    if (i < M.n_rows) static_cast<T *>(M.y)[y_perm ? i : M.perm[i]] = acc;
+}
+
+template <class T, bool JD, int BR>
+__global__ __launch_bounds__(kBlock) void batch_persistent_kernel(const Member *__restrict__ members,
+                                                                  const Tile *__restrict__ tiles,
+                                                                  int32_t n_tiles, int32_t *counter,
+                                                                  uint32_t flags) {
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0);
+        if (t >= n_tiles) return;                  // every wave ends here once the table is drained
+        const Tile tile = tiles[t];
+        const Member M = members[tile.m];
+        for (int64_t g = tile.g0; g < tile.g1; ++g) wave_group<T, JD, BR>(M, g, y_perm);
+    }
+}
+
+__global__ void reset_counter_kernel(int32_t *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <class T, bool JD, int BR>
+void launch_persistent(int grid, const Member *m, const Tile *t, int32_t nt, int32_t *c, uint32_t f, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, c);
+    hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+}
+
+}  // namespace
+}  // namespace pjds
+
+using namespace pjds;
+
+struct pjds_batch {
+    int32_t mode = 0, dtype = 0, n_members = 0, n_tiles = 0;
+    uint32_t flags = 0;
+    bool jd = true;
+    int32_t block_height = 64;
+    int grid = 0;
+    std::vector<pjds_batch_member> members;       // host copies of the descriptors
+    std::vector<pjds_info> infos;
+    Member *d_members = nullptr;
+    Tile *d_tiles = nullptr;
+    int32_t *d_counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(PJDS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release(pjds_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_members) (void)hipFree(b->d_members);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+}
+
+// Enqueue the batch's work on stream s (used directly, or under graph capture).
+int enqueue(pjds_batch *b, hipStream_t s) {
+    if (b->mode == PJDS_BATCH_PERSISTENT) {
+        const bool jd = b->jd;
+        const int br = b->block_height;
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            if (jd) {
+                if (br == 32) launch_persistent<T, true, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                else if (br == 64) launch_persistent<T, true, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                else launch_persistent<T, true, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+            } else {
+                if (br == 32) launch_persistent<T, false, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                else if (br == 64) launch_persistent<T, false, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                else launch_persistent<T, false, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+            }
+        };
+        if (b->dtype == PJDS_F64) go(double{});
+        else go(float{});
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? PJDS_OK : hip_fail(e, "persistent batch launch");
+    }
+    for (int32_t k = 0; k < b->n_members; ++k) {
+        const pjds_batch_member &m = b->members[size_t(k)];
+        pjds_info info = b->infos[size_t(k)];
+        info.split_len = 0;                        // rows are never split in a batch
+        info.n_chunks = 0;
+        int rc = pjds_spmv(&info, m.d_row_len, m.d_offsets, m.d_col_p, m.d_val_p, m.d_perm,
+                           nullptr, nullptr, b->dtype, m.d_x, m.d_y, b->flags, s);
+        if (rc) return rc;
+    }
+    return PJDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
+                      uint32_t flags, int32_t mode, int32_t groups_per_tile, pjds_batch **out) {
+    if (!out) return fail(PJDS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_members < 1 || !members) return fail(PJDS_ERR_ARG, "empty batch");
+    if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
+    if (flags & ~PJDS_Y_PERMUTED) return fail(PJDS_ERR_ARG, "unsupported batch flags 0x%x", flags);
+    if (mode != PJDS_BATCH_PERSISTENT && mode != PJDS_BATCH_GRAPH && mode != PJDS_BATCH_DIRECT)
+        return fail(PJDS_ERR_ARG, "mode %d", mode);
+    if (groups_per_tile <= 0) groups_per_tile = 8;
+    const pjds_info &first = *members[0].info;
+    for (int32_t k = 0; k < n_members; ++k) {
+        const pjds_batch_member &m = members[k];
+        if (!m.info) return fail(PJDS_ERR_ARG, "member %d: info is NULL", k);
+        const pjds_info &in = *m.info;
+        if (in.block_height != first.block_height || (in.flags & PJDS_LAYOUT_BLOCK) != (first.flags & PJDS_LAYOUT_BLOCK))
+            return fail(PJDS_ERR_ARG, "member %d: every member needs the same block height and layout", k);
+        if (in.n_rows < 0 || in.n_pad < in.n_rows || in.n_pad % in.block_height)
+            return fail(PJDS_ERR_ARG, "member %d: inconsistent info", k);
+        if (in.n_rows && (!m.d_row_len || !m.d_offsets || !m.d_y))
+            return fail(PJDS_ERR_ARG, "member %d: NULL device array", k);
+        if (in.nnz_stored && (!m.d_col_p || !m.d_val_p || !m.d_x))
+            return fail(PJDS_ERR_ARG, "member %d: NULL device array", k);
+        if (in.n_rows && !(flags & PJDS_Y_PERMUTED) && !m.d_perm)
+            return fail(PJDS_ERR_ARG, "member %d: d_perm is NULL (needed to scatter y)", k);
+        if (ceil_div(in.n_pad, kWave) > INT32_MAX) return fail(PJDS_ERR_OVERFLOW, "member %d too large", k);
+    }
+    pjds_batch *b = new (std::nothrow) pjds_batch;
+    if (!b) return fail(PJDS_ERR_NOMEM, "host allocation failed");
+    b->mode = mode;
+    b->dtype = dtype;
+    b->flags = flags;
+    b->n_members = n_members;
+    b->jd = !(first.flags & PJDS_LAYOUT_BLOCK);
+    b->block_height = first.block_height;
+    b->members.assign(members, members + n_members);
+    for (int32_t k = 0; k < n_members; ++k) b->infos.push_back(*members[k].info);
+
+    if (mode == PJDS_BATCH_PERSISTENT) {
+        std::vector<Member> dm(static_cast<size_t>(n_members));
+        std::vector<Tile> tiles;
+        std::vector<double> cost;
+        for (int32_t k = 0; k < n_members; ++k) {
+            const pjds_batch_member &m = members[k];
+            const pjds_info &in = *m.info;
+            dm[size_t(k)] = Member{m.d_row_len, m.d_offsets, m.d_col_p, m.d_val_p, m.d_perm, m.d_x, m.d_y, in.n_rows, in.n_pad};
+            const int64_t groups = ceil_div(in.n_pad, kWave);
+            const double per_group = in.n_pad ? double(in.nnz_stored) / double(in.n_pad) * kWave : 0.0;
+            for (int64_t g = 0; g < groups; g += groups_per_tile) {
+                const int64_t g1 = std::min(groups, g + groups_per_tile);
+                tiles.push_back(Tile{k, int32_t(g), int32_t(g1), 0});
+                cost.push_back(per_group * double(g1 - g));
+            }
+        }
+        if (tiles.size() > size_t(INT32_MAX)) { release(b); return fail(PJDS_ERR_OVERFLOW, "too many tiles"); }
+        // longest tiles first; ties by (member, position) keep the order deterministic
+        std::vector<size_t> order(tiles.size());
+        std::iota(order.begin(), order.end(), size_t(0));
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
+        std::vector<Tile> sorted(tiles.size());
+        for (size_t q = 0; q < order.size(); ++q) sorted[q] = tiles[order[q]];
+        b->n_tiles = int32_t(sorted.size());
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) { release(b); return hip_fail(e, "device query"); }
+        b->grid = std::max(1, cus) * 8;            // 8 workgroups (32 waves) per CU
+        e = hipMalloc(&b->d_members, sizeof(Member) * dm.size());
+        if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(Tile) * std::max<size_t>(sorted.size(), 1));
+        if (e == hipSuccess) e = hipMalloc(&b->d_counter, 256);
+        if (e == hipSuccess) e = hipMemcpy(b->d_members, dm.data(), sizeof(Member) * dm.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !sorted.empty()) e = hipMemcpy(b->d_tiles, sorted.data(), sizeof(Tile) * sorted.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { release(b); return hip_fail(e, "batch tables"); }
+    }
+    if (mode != PJDS_BATCH_DIRECT) {
+        // capture on a private stream (the default stream cannot be captured)
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) { release(b); return hip_fail(e, "capture stream"); }
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? enqueue(b, cs) : hip_fail(e, "begin capture");
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        b->graph = g;
+        if (rc == PJDS_OK && e2 != hipSuccess) rc = hip_fail(e2, "end capture");
+        if (rc == PJDS_OK) {
+            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(e, "graph instantiate");
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc) { release(b); return rc; }
+    }
+    *out = b;
+    return PJDS_OK;
+}
+
+int pjds_batch_launch(pjds_batch *b, void *stream) {
+    if (!b) return fail(PJDS_ERR_ARG, "batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->mode == PJDS_BATCH_DIRECT) return enqueue(b, s);
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    return e == hipSuccess ? PJDS_OK : hip_fail(e, "graph launch");
+}
+
+int pjds_batch_info(const pjds_batch *b, int32_t *n_tiles, int32_t *grid) {
+    if (!b) return fail(PJDS_ERR_ARG, "batch is NULL");
+    if (n_tiles) *n_tiles = b->n_tiles;
+    if (grid) *grid = b->grid;
+    return PJDS_OK;
+}
+
+int pjds_batch_destroy(pjds_batch *b) {
+    release(b);
+    return PJDS_OK;
+}
+
+}  // extern "C"

@@ -7,13 +7,15 @@
 // segment of that block (64 values, 64 indices) is one coalesced 512 B + 256 B access per
 // step.  b_r = 32 puts two blocks in a wave, b_r = 128 spreads a block over two waves; the
 // loop bound is always the wave's own longest row, and each lane masks its arithmetic with
-// its own row length, so padding never enters a sum.
+// its own row length, so padding never enters a sum.  A lane past the end of its row
+// re-reads the slot of the wave's longest row (the "lead" lane) instead of its own padding
+// slot: that address and the x element it points to are already being fetched for the lead,
+// so padding costs neither HBM traffic nor extra cache lines.
 //
 // Streams.  Values and column indices are read exactly once per product, so they are
 // loaded non-temporally; x goes through the normal cached path (it is re-read by every
-// row that references it).  Workgroups are renumbered so that each XCD (8 per MI355X, each
-// with its own L2) processes one contiguous range of row blocks, which keeps the x window
-// of neighbouring blocks in that XCD's L2.
+// row that references it).  With PJDS_XCD_REMAP workgroups are renumbered so that each XCD
+// (8 per MI355X, each with its own L2) processes one contiguous range of row blocks.
 //
 // Long rows.  Wave groups whose longest row exceeds split_len are cut into work items of
 // split_len steps, scheduled first.  Each item writes its 64 partial sums to the workspace;
@@ -32,7 +34,10 @@ namespace {
 
 constexpr int kBlock = 256;               // threads per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kUnroll = 8;                // independent entries in flight per lane
+#ifndef PJDS_UNROLL
+#define PJDS_UNROLL 8
+#endif
+constexpr int kUnroll = PJDS_UNROLL;      // independent entries in flight per lane
 constexpr uint32_t kXcds = 8;
 
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
@@ -43,7 +48,7 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
 }
 
 __device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
-    return (flags & PJDS_NO_XCD_REMAP) ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    return (flags & PJDS_XCD_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -55,42 +60,78 @@ __device__ __forceinline__ int wave_max(int v) {
 template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
-// Sum of row entries j in [j0, j1) for the calling lane (row i, length len), Listing 2's
-// inner loop.  j1 is wave-uniform and <= the wave's longest row.
-template <class T, bool JD, int BR>
-__device__ __forceinline__ T row_range_sum(int64_t i, int len, int j0, int j1,
-                                           const int64_t *__restrict__ offsets,
-                                           const int32_t *__restrict__ col_p,
-                                           const T *__restrict__ val_p,
-                                           const T *__restrict__ x) {
-    // Block layout: entry j of row i at block_start[i / BR] + j*BR + i % BR.
-    const int64_t base = JD ? i : offsets[i / BR] + (i % BR);
-    T acc = T(0);
-    for (int jb = j0; jb < j1; jb += kUnroll) {
-        T v[kUnroll];
-        int32_t c[kUnroll];
+// Lowest lane of the wave whose row is the longest (len == m, m > 0).
+__device__ __forceinline__ int lead_lane(int len, int m) {
+    return __builtin_ctzll(__ballot(len == m));
+}
+
+// Where entry j of a row lives, given the row's base position b (see each format).
+template <bool JD, int BR>
+struct PjdsAddr {                       // JD: col_start[j] + i;  block: block_start + j*BR + r
+    const int64_t *off;
+    __device__ int64_t base(int64_t i) const { return JD ? i : off[i / BR] + (i % BR); }
+    __device__ int64_t operator()(int j, int64_t b) const { return JD ? off[j] + b : b + int64_t(j) * BR; }
+};
+struct EllrAddr {                       // ELLPACK-R: j * n_pad + i
+    int64_t n_pad;
+    __device__ int64_t base(int64_t i) const { return i; }
+    __device__ int64_t operator()(int j, int64_t b) const { return int64_t(j) * n_pad + b; }
+};
+
+// U consecutive entries j in [jb, jb+U) (all below the wave's longest row) added into acc:
+// U independent value/index loads, then U gathers, then U FMAs.  A lane past the end of its
+// row reads the lead row's slot (an entry that exists for every such j) and keeps acc.
+// The gather reads X[c * ldx + xoff] (ldx = 1, xoff = 0 for a single vector).
+template <int U, class T, class Addr>
+__device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base, int64_t base_lead,
+                                          const Addr &addr, const int32_t *__restrict__ col_p,
+                                          const T *__restrict__ val_p, const T *__restrict__ x,
+                                          int64_t ldx, int64_t xoff) {
+    T v[U];
+    int32_t c[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int j = jb + u;
-            const int jc = j < j1 ? j : j1 - 1;       // uniform clamp keeps offsets[] in range
-            int64_t a = JD ? offsets[jc] + base : base + int64_t(jc) * BR;
-            // With BR >= 64 every slot below the wave maximum exists (it is padding at
-            // worst).  With BR == 32 the second block of the wave may be shorter: lanes past
-            // their own row read slot 0 instead, which always exists.
-            if (BR < kWave) a = jc < len ? a : 0;
-            v[u] = ld_stream(val_p + a);
-            c[u] = ld_stream(col_p + a);
-        }
-        T xv[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) xv[u] = x[c[u]];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int j = jb + u;
-            const T s = __builtin_fma(v[u], xv[u], acc);
-            acc = (j < len && j < j1) ? s : acc;
-        }
+    for (int u = 0; u < U; ++u) {
+        const int j = jb + u;
+        const int64_t a = addr(j, j < len ? base : base_lead);
+        v[u] = ld_stream(val_p + a);
+        c[u] = ld_stream(col_p + a);
     }
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[int64_t(c[u]) * ldx + xoff];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const T s = __builtin_fma(v[u], xv[u], acc);
+        acc = jb + u < len ? s : acc;
+    }
+}
+
+// Sum of the calling lane's row entries j in [j0, j1) (Listing 1 / Listing 2 inner loop).
+// j1 is wave-uniform and <= the wave's longest row, which is row i_lead.  Full groups of
+// kUnroll steps, then an 8/4/2/1 tail, so no load is issued past j1.
+template <class T, class Addr>
+__device__ __forceinline__ T row_range_sum(int64_t i, int64_t i_lead, int len, int j0, int j1,
+                                           const Addr &addr, const int32_t *__restrict__ col_p,
+                                           const T *__restrict__ val_p, const T *__restrict__ x,
+                                           int64_t ldx = 1, int64_t xoff = 0) {
+    const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
+    T acc = T(0);
+    int jb = j0;
+    for (; jb + kUnroll <= j1; jb += kUnroll)
+        row_steps<kUnroll>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+    if (kUnroll > 8 && jb + 8 <= j1) {
+        row_steps<8>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        jb += 8;
+    }
+    if (kUnroll > 4 && jb + 4 <= j1) {
+        row_steps<4>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        jb += 4;
+    }
+    if (kUnroll > 2 && jb + 2 <= j1) {
+        row_steps<2>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        jb += 2;
+    }
+    if (jb < j1) row_steps<1>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
     return acc;
 }
 
@@ -112,8 +153,9 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
         const int64_t i = int64_t(g) * kWave + lane;
         const int len = i < n_pad ? row_len[i] : 0;
         const int m = wave_max(len);
+        const int64_t i_lead = i - lane + lead_lane(len, m);
         const int j0 = c * split_len, j1 = min(j0 + split_len, m);
-        const T part = row_range_sum<T, JD, BR>(i, len, j0, j1, offsets, col_p, val_p, x);
+        const T part = row_range_sum(i, i_lead, len, j0, j1, PjdsAddr<JD, BR>{offsets}, col_p, val_p, x);
         partials[w * kWave + lane] = part;
         __threadfence();                                    // publish the partial sums
         int last = 0;
@@ -135,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     const int len = i < n_pad ? row_len[i] : 0;
     const int m = wave_max(len);
     if (split_len > 0 && m > split_len) return;            // done by the work items above
-    const T acc = row_range_sum<T, JD, BR>(i, len, 0, m, offsets, col_p, val_p, x);
+    const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : i;
+    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, x);
     if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
 }
 
@@ -144,56 +187,33 @@ __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
 }
 
 // ---- pJDS with k right-hand sides -----------------------------------------------------
-template <class T, bool JD, int BR, int TILE>
+// LPR consecutive lanes share one sorted row and each takes one right-hand side of the
+// current tile of LPR vectors: the matrix entry is loaded once for the whole tile, and the
+// LPR lanes gather LPR consecutive doubles of one row of the interleaved X (X[c*k + v]),
+// so a gather instruction touches about 64/LPR cache lines instead of 64.  A wave covers
+// R = 64/LPR consecutive sorted rows; tiles over k run in gridDim.y.
+template <class T, bool JD, int BR, int LPR>
 __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
-    int64_t n_rows, int64_t n_pad, int64_t n_groups, int32_t k,
+    int64_t n_rows, int64_t n_pad, int64_t n_waves, int32_t k,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
     const int32_t *__restrict__ perm, const T *__restrict__ X, T *__restrict__ Y, uint32_t flags) {
+    constexpr int R = kWave / LPR;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t g = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
-    if (g >= n_groups) return;
-    const int v0 = blockIdx.y * TILE;
-    const int tv = min(TILE, k - v0);
-    const int64_t i = g * kWave + lane;
+    const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (w >= n_waves) return;
+    const int v = int(blockIdx.y) * LPR + lane % LPR;      // this lane's right-hand side
+    const int vc = v < k ? v : k - 1;
+    const int64_t i = w * R + lane / LPR;
     const int len = i < n_pad ? row_len[i] : 0;
     const int m = wave_max(len);
-    const int64_t base = JD ? i : offsets[i / BR] + (i % BR);
-    T acc[TILE];
-#pragma unroll
-    for (int t = 0; t < TILE; ++t) acc[t] = T(0);
-    constexpr int U = TILE >= 4 ? 2 : 4;
-    for (int jb = 0; jb < m; jb += U) {
-        T v[U];
-        int32_t c[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = jb + u;
-            const int jc = j < m ? j : m - 1;
-            int64_t a = JD ? offsets[jc] + base : base + int64_t(jc) * BR;
-            if (BR < kWave) a = jc < len ? a : 0;
-            v[u] = ld_stream(val_p + a);
-            c[u] = ld_stream(col_p + a);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool on = jb + u < len && jb + u < m;
-            const T *xr = X + int64_t(c[u]) * k + v0;
-#pragma unroll
-            for (int t = 0; t < TILE; ++t) {
-                if (t < tv) {
-                    const T s = __builtin_fma(v[u], xr[t], acc[t]);
-                    acc[t] = on ? s : acc[t];
-                }
-            }
-        }
+    if (m == 0) {
+        if (i < n_rows && v < k) Y[int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v] = T(0);
+        return;
     }
-    if (i < n_rows) {
-        T *yr = Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v0;
-#pragma unroll
-        for (int t = 0; t < TILE; ++t)
-            if (t < tv) yr[t] = acc[t];
-    }
+    const int64_t i_lead = w * R + lead_lane(len, m) / LPR;
+    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, X, k, vc);
+    if (i < n_rows && v < k) Y[int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v] = acc;
 }
 
 // ---- ELLPACK-R, Listing 1 -------------------------------------------------------------
@@ -205,26 +225,9 @@ __global__ __launch_bounds__(kBlock) void ellr_spmv_kernel(
     const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     const int len = i < n_pad ? rowmax[i] : 0;
     const int m = wave_max(len);
-    T acc = T(0);
-    for (int jb = 0; jb < m; jb += kUnroll) {
-        T v[kUnroll];
-        int32_t c[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int j = jb + u < m ? jb + u : m - 1;
-            const int64_t a = int64_t(j) * n_pad + (i < n_pad ? i : 0);
-            v[u] = ld_stream(val_e + a);
-            c[u] = ld_stream(col_e + a);
-        }
-        T xv[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) xv[u] = x[c[u]];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const T s = __builtin_fma(v[u], xv[u], acc);
-            acc = (jb + u < len) ? s : acc;
-        }
-    }
+    // lanes past their row read the slot of the wave's longest row (never padding)
+    const int64_t i_lead = m > 0 ? i - (threadIdx.x & (kWave - 1)) + lead_lane(len, m) : 0;
+    const T acc = row_range_sum(i, i_lead, len, 0, m, EllrAddr{n_pad}, col_e, val_e, x);
     if (i < n_rows) y[i] = acc;
 }
 
@@ -319,19 +322,22 @@ template <class T, bool JD, int BR>
 void launch_spmmv(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
                   const void *vp, const int32_t *perm, int32_t k, int32_t t, const void *X,
                   void *Y, uint32_t flags, hipStream_t s) {
-    const int64_t groups = ceil_div(in.n_pad, kWave);
-    const dim3 grid(unsigned(ceil_div(groups, kWavesPerBlock)), unsigned(ceil_div(k, t)));
 #define PJDS_SPMMV_CASE(TT)                                                                           \
-    case TT:                                                                                          \
+    case TT: {                                                                                        \
+        const int64_t waves = ceil_div(in.n_pad, kWave / TT);                                        \
+        const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(ceil_div(k, TT)));       \
         hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, TT>), grid, dim3(kBlock), 0, s, in.n_rows,  \
-                           in.n_pad, groups, k, rl, off, cp, static_cast<const T *>(vp), perm,        \
+                           in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,         \
                            static_cast<const T *>(X), static_cast<T *>(Y), flags);                    \
-        break;
+        break;                                                                                        \
+    }
     switch (t) {
         PJDS_SPMMV_CASE(1)
         PJDS_SPMMV_CASE(2)
         PJDS_SPMMV_CASE(4)
         PJDS_SPMMV_CASE(8)
+        PJDS_SPMMV_CASE(16)
+        PJDS_SPMMV_CASE(32)
     }
 #undef PJDS_SPMMV_CASE
 }
@@ -405,7 +411,7 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x, void *d_y,
               uint32_t flags, void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
-    if (flags & ~(PJDS_Y_PERMUTED | PJDS_NO_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
@@ -422,10 +428,11 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
                int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
                uint32_t flags, void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
-    if (flags & ~(PJDS_Y_PERMUTED | PJDS_NO_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
     if (k < 1) return fail(PJDS_ERR_ARG, "k = %d", k);
     const int32_t t = vectors_per_tile;
-    if (t != 1 && t != 2 && t != 4 && t != 8) return fail(PJDS_ERR_ARG, "vectors_per_tile %d: must be 1, 2, 4 or 8", t);
+    if (t != 1 && t != 2 && t != 4 && t != 8 && t != 16 && t != 32)
+        return fail(PJDS_ERR_ARG, "vectors_per_tile %d: must be 1, 2, 4, 8, 16 or 32", t);
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_Y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_X)) return fail(PJDS_ERR_ARG, "NULL device array");

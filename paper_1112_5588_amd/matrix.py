@@ -62,6 +62,17 @@ class PjdsMatrix:
                              else v[:info.nnz_stored]) for k, v in h.items()}
         return self
 
+    @classmethod
+    def from_arrays(cls, n_rows: int, n_cols: int, row_ptr, col, val, **kw) -> "PjdsMatrix":
+        """From CSR arrays given as numpy arrays or torch tensors (device tensors are copied to
+        the host for the conversion)."""
+        class _A:
+            pass
+        A = _A()
+        A.n_rows, A.n_cols = n_rows, n_cols
+        A.row_ptr, A.col, A.val = (a.cpu().numpy() if isinstance(a, torch.Tensor) else a for a in (row_ptr, col, val))
+        return cls.from_csr(A, **kw)
+
     @property
     def n_rows(self) -> int:
         return self.info.n_rows
@@ -71,18 +82,20 @@ class PjdsMatrix:
         return self.info.n_cols
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, y_permuted: bool = False,
-             xcd_remap: bool = True, stream=None) -> torch.Tensor:
+             xcd_remap: bool = False, stream=None) -> torch.Tensor:
         if y is None:
             y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
-        flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (0 if xcd_remap else L.PJDS_NO_XCD_REMAP)
+        flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
         d = self.d
         L.pjds_spmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"],
                     d["sched"] if self.info.n_chunks else None, d["work"], x, y, flags, stream)
         return y
 
-    def spmmv(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int = 4,
+    def spmmv(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int | None = None,
               y_permuted: bool = False, stream=None) -> torch.Tensor:
         k = X.shape[1]
+        if vectors_per_tile is None:
+            vectors_per_tile = min(32, 1 << (k - 1).bit_length())
         if Y is None:
             Y = torch.empty((self.info.n_rows, k), dtype=self.dtype, device=self.device)
         flags = L.PJDS_Y_PERMUTED if y_permuted else 0
@@ -159,3 +172,37 @@ class CsrMatrix:
     def footprint_bytes(self) -> int:
         vb = 8 if self.dtype == torch.float64 else 4
         return self.nnz * (vb + 4) + (self.n_rows + 1) * 8
+
+
+class PjdsBatch:
+    """y_m = A_m x_m for many pJDS matrices in one call (pjds_batch_* of include/pjds.h).
+
+    ``mats`` are PjdsMatrix objects of one block height and layout; ``xs``/``ys`` their
+    device vectors.  The object keeps references to everything the handle points at.
+    """
+
+    def __init__(self, mats, xs, ys, mode: int = L.PJDS_BATCH_PERSISTENT, y_permuted: bool = False,
+                 groups_per_tile: int = 0):
+        self.mats, self.xs, self.ys = list(mats), list(xs), list(ys)
+        members = [(M.info, M.d["row_len"], M.d["offsets"], M.d["col_p"], M.d["val_p"], M.d["perm"], x, y)
+                   for M, x, y in zip(self.mats, self.xs, self.ys)]
+        self.handle = L.pjds_batch_create(members, self.mats[0].dtype,
+                                          L.PJDS_Y_PERMUTED if y_permuted else 0, mode, groups_per_tile)
+
+    def launch(self, stream=None) -> None:
+        L.pjds_batch_launch(self.handle, stream)
+
+    def info(self) -> tuple[int, int]:
+        return L.pjds_batch_info(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            L.pjds_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "CSR", "stream_u64", "uniform01", "uniform_pm1", "normal",
     "laplacian_2d", "hh_like", "powerlaw", "banded_random", "random_csr",
-    "uneven_batch_sizes", "dense_x",
+    "uneven_batch_sizes", "dense_x", "banded_stratified",
 ]
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -293,6 +293,37 @@ def banded_random(n: int, seed: int, len_lo: int = 3, len_hi: int = 60, halo: in
     np.cumsum(lens, out=row_ptr[1:])
     val = uniform_pm1(seed, 3, int(row_ptr[-1]))
     return CSR(n, n, row_ptr, col, val, f"banded_n{n}_s{seed}")
+
+
+def banded_stratified(n: int, seed: int, len_lo: int = 3, len_hi: int = 60, halo: int = 4096) -> CSR:
+    """Square matrix, row lengths uniform in [len_lo, len_hi], values uniform in [-1, 1).
+
+    Row i's columns are spread over the window [i - halo, i + halo] clipped to the matrix:
+    the window is cut into L_i equal strata and column j is uniform within stratum j, so
+    columns are distinct and ascending by construction (stratified uniform sampling).
+    ``synth.torchgen.banded_stratified`` computes the same arrays bit for bit with torch.
+    """
+    lens = _uniform_int(seed, 1, n, len_lo, len_hi)
+    i = np.arange(n, dtype=np.int64)
+    lo = np.maximum(0, i - halo)
+    width = np.minimum(n - 1, i + halo) - lo + 1
+    lens = np.minimum(lens, width)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    row = np.repeat(i, lens)
+    j = np.arange(nnz, dtype=np.int64) - row_ptr[row]
+    L = lens[row]
+    w = width[row]
+    # stratum j covers [floor(j*w/L), floor((j+1)*w/L)); pick uniformly inside it
+    s0 = (j * w) // L
+    s1 = ((j + 1) * w) // L
+    z = stream_u64(seed, 2, nnz) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        off = ((z * (s1 - s0).astype(np.uint64)) >> np.uint64(32)).astype(np.int64)
+    col = (lo[row] + s0 + off).astype(np.int32)
+    val = uniform_pm1(seed, 3, nnz)
+    return CSR(n, n, row_ptr, col, val, f"stratified_n{n}_s{seed}")
 
 
 def uneven_batch_sizes(count: int = 512, lo: int = 1000, hi: int = 500_000, seed: int = 999) -> np.ndarray:

@@ -144,3 +144,19 @@ def test_device_entry_points_validate_before_touching_the_gpu():
     assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 3, None, None, 0, None) == L.PJDS_ERR_ARG
     assert lib.csr_spmv(10, 10, None, None, None, 0, None, None, 5, None) == L.PJDS_ERR_ARG
     assert lib.pjds_probe(3, None, None, 10, None) == L.PJDS_ERR_ARG
+
+
+def test_batch_create_validates_on_the_host():
+    A = synth.random_csr(100, 100, 1)
+    i64 = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, block_height=64)
+    i32 = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, block_height=32)
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    arr = (L.pjds_batch_member * 2)()
+    arr[0] = L.pjds_batch_member(ctypes.pointer(i64), None, None, None, None, None, None, None)
+    arr[1] = L.pjds_batch_member(ctypes.pointer(i32), None, None, None, None, None, None, None)
+    assert lib.pjds_batch_create(2, arr, 0, 0, 0, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert lib.pjds_batch_create(0, arr, 0, 0, 0, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert lib.pjds_batch_create(1, arr, 0, 0, 9, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert lib.pjds_batch_create(1, arr, 0, 0x40, 0, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert h.value is None

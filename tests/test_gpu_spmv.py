@@ -171,7 +171,7 @@ def test_csr_parity(dtype, variant):
 # ------------------------------------------------------------------ many right-hand sides
 
 @pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 32])
-@pytest.mark.parametrize("t", [1, 2, 4, 8])
+@pytest.mark.parametrize("t", [1, 2, 4, 8, 16, 32])
 def test_spmmv_config1(k, t):
     A = synth.laplacian_2d(128)
     X = synth.dense_x(A.n_cols, 40, k=k).reshape(A.n_cols, k)

@@ -172,7 +172,7 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
  * block height and layout, any sizes).  Modes:
  *   PJDS_BATCH_PERSISTENT  one persistent kernel: the members' rows are cut into tiles of
  *                          `groups_per_tile` wave groups (64 sorted rows each; <= 0 -> 8),
- *                          ordered by estimated work, longest first; each wave pulls tiles
+ *                          member by member, largest member first; each wave pulls tiles
  *                          from one device counter until none is left.  A fill kernel resets
  *                          the counter first.  Both are captured once in a HIP graph.
  *   PJDS_BATCH_GRAPH       one pjds_spmv launch per member, captured in a HIP graph.
@@ -235,6 +235,50 @@ int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_c
 int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int32_t *d_col,
              const void *d_val, int32_t dtype, const void *d_x, void *d_y, int32_t variant,
              void *stream);
+
+/* ---- learned tuner: features -------------------------------------------------------- */
+/*
+ * 24 features of a CSR matrix (host arrays) for the configuration tuner, written to out[24]:
+ *  0 log2 N, 1 log2(nnz+1), 2-5 mean, std, skewness, excess kurtosis of the row lengths,
+ *  6 min, 7 log2(max+1), 8 max/mean, 9 empty-row fraction, 10-12 p50/p90/p99 over the mean,
+ *  13 log2 of ELLPACK-R stored/nnz, 14-15 pJDS stored/nnz at block height 64 with a global
+ *  sort and with a 4096-row sort window (the padding of Sect. 2.1), 16-18 max/mean/std of
+ *  |col-row| / max(N, n_cols), 19-20 fractions with |col-row| <= 64 and <= 4096, 21 log of
+ *  distinct offsets per entry, 22 share of the 16 most used offsets, 23 entries per distinct
+ *  128-byte x line in 64-row blocks (a proxy of the right-hand-side reuse alpha of eq. (1)).
+ * Offset statistics use every s-th entry, s = ceil(nnz / 2^20).  O(N log N + nnz).
+ */
+int pjds_features(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, const int32_t *col_idx,
+                  float *out);
+
+/* ---- learned tuner: the network ----------------------------------------------------- */
+/*
+ * Three-layer perceptron d_in -> 64 -> 64 -> d_out with ReLU after the hidden layers,
+ * binary32, predicting a standardised run time per kernel configuration.  Parameters are
+ * one packed device array [W1 (d_in x 64) | b1 (64) | W2 (64 x 64) | b2 (64) | W3 (64 x
+ * d_out) | b3 (d_out)], weights (fan_in, fan_out) row-major; 1 <= d_in, d_out <= 64.
+ * X [batch x d_in], T and M [batch x d_out] are row-major device arrays; M is a 0/1 mask of
+ * the labels present.  Loss = sum(M (P - T)^2) / sum(M).  Deterministic: the gradient is
+ * summed over 64-row tiles in tile order.  Asynchronous on `stream`.
+ */
+int mlp_param_count(int32_t d_in, int32_t d_out, int64_t *n);
+/* Device workspace of mlp_backward for a batch (bytes). */
+int mlp_workspace_size(int32_t d_in, int32_t d_out, int64_t batch, int64_t *bytes);
+/* P [batch x d_out] = network(X). */
+int mlp_forward(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch, const float *d_X,
+                float *d_P, void *stream);
+/* d_grad [n_params] = gradient of the loss; *d_loss (device, may be NULL) = the loss. */
+int mlp_backward(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch, const float *d_X,
+                 const float *d_T, const float *d_M, float *d_grad, float *d_loss, void *d_work,
+                 void *stream);
+/* One Adam update (Kingma and Ba, 2015) at 1-based `step` with bias correction. */
+int mlp_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t n,
+                  int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+/* Per row: idx = argmin over outputs c with valid[c] != 0 of P*scale[c] + shift[c] (scale,
+ * shift, valid may be NULL = 1, 0, all valid) and margin = runner-up minus best. */
+int mlp_infer(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch, const float *d_X,
+              const float *d_scale, const float *d_shift, const float *d_valid, int32_t *d_idx,
+              float *d_margin, void *stream);
 
 /* ---- measurement helpers ------------------------------------------------------------ */
 /* Stream probes for the achievable bandwidth ceiling: mode 0 reads n doubles and writes one

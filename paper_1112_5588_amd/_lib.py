@@ -85,6 +85,13 @@ _SIGS = {
     "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "csr_spmv": [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp],
     "pjds_probe": [_i32, _vp, _vp, _i64, _vp],
+    "pjds_features": [_i64, _i64, _vp, _vp, _vp],
+    "mlp_param_count": [_i32, _i32, ctypes.POINTER(_i64)],
+    "mlp_workspace_size": [_i32, _i32, _i64, ctypes.POINTER(_i64)],
+    "mlp_forward": [_vp, _i32, _i32, _i64, _vp, _vp, _vp],
+    "mlp_backward": [_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "mlp_adam_step": [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp],
+    "mlp_infer": [_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "pjds_batch_create": [_i32, ctypes.POINTER(pjds_batch_member), _i32, _u32, _i32, _i32, ctypes.POINTER(_vp)],
     "pjds_batch_launch": [_vp, _vp],
     "pjds_batch_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
@@ -266,3 +273,43 @@ def pjds_batch_info(handle: int) -> tuple[int, int]:
 
 def pjds_batch_destroy(handle: int) -> None:
     _check(lib().pjds_batch_destroy(handle), "pjds_batch_destroy")
+
+
+def pjds_features(n_rows: int, n_cols: int, row_ptr, col_idx) -> np.ndarray:
+    out = np.zeros(24, np.float32)
+    _check(lib().pjds_features(n_rows, n_cols, _host(row_ptr, np.int64), _host(col_idx, np.int32),
+                               _host(out)), "pjds_features")
+    return out
+
+
+def mlp_param_count(d_in: int, d_out: int) -> int:
+    n = _i64(0)
+    _check(lib().mlp_param_count(d_in, d_out, ctypes.byref(n)), "mlp_param_count")
+    return n.value
+
+
+def mlp_workspace_size(d_in: int, d_out: int, batch: int) -> int:
+    n = _i64(0)
+    _check(lib().mlp_workspace_size(d_in, d_out, batch, ctypes.byref(n)), "mlp_workspace_size")
+    return n.value
+
+
+def mlp_forward(d_params, d_in: int, d_out: int, d_X, d_P, stream=None) -> None:
+    _check(lib().mlp_forward(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_P),
+                             _stream(stream)), "mlp_forward")
+
+
+def mlp_backward(d_params, d_in: int, d_out: int, d_X, d_T, d_M, d_grad, d_loss, d_work, stream=None) -> None:
+    _check(lib().mlp_backward(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_T), _dev(d_M),
+                              _dev(d_grad), _dev(d_loss), _dev(d_work), _stream(stream)), "mlp_backward")
+
+
+def mlp_adam_step(d_params, d_grad, d_m, d_v, step: int, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(lib().mlp_adam_step(_dev(d_params), _dev(d_grad), _dev(d_m), _dev(d_v), d_params.numel(), step,
+                               lr, beta1, beta2, eps, _stream(stream)), "mlp_adam_step")
+
+
+def mlp_infer(d_params, d_in: int, d_out: int, d_X, d_scale, d_shift, d_valid, d_idx, d_margin, stream=None) -> None:
+    _check(lib().mlp_infer(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_scale), _dev(d_shift),
+                           _dev(d_valid), _dev(d_idx), _dev(d_margin), _stream(stream)), "mlp_infer")

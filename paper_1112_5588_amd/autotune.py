@@ -1,0 +1,188 @@
+"""Exhaustive autotuner over kernel configurations for y = A x.
+
+For a matrix it converts once per distinct storage (format, block height, sort window,
+layout, long-row split), times every catalog entry that uses it (median of `reps`
+launches, each bracketed by HIP events on the launch stream, after `warmup` launches), and
+returns the fastest.  It is the reference the learned tuner is judged against (regret 0 by
+definition) and its fallback.
+
+Results can be appended to a JSON-lines store keyed by (matrix key, configuration,
+device), so a long sweep resumes where it stopped.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .matrix import CsrMatrix, EllrMatrix, PjdsMatrix
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    fmt: str                    # "pjds", "ellr" or "csr"
+    block_height: int = 64
+    layout: str = "jd"
+    sort_window: int = 0
+    split_len: int = 0
+    xcd_remap: bool = False
+    variant: int = 1            # CSR lanes per row
+
+    def storage_key(self):
+        if self.fmt == "pjds":
+            return ("pjds", self.block_height, self.layout, self.sort_window, self.split_len)
+        return (self.fmt,)
+
+
+# Index 0 is the untuned default: the paper's format with a block height of one wavefront,
+# global sort, jagged-diagonal layout, x through the caches.
+CATALOG: tuple[Config, ...] = (
+    Config("pjds_b64_jd", "pjds", 64, "jd"),
+    Config("pjds_b32_jd", "pjds", 32, "jd"),
+    Config("pjds_b128_jd", "pjds", 128, "jd"),
+    Config("pjds_b64_jd_xcd", "pjds", 64, "jd", xcd_remap=True),
+    Config("pjds_b64_w256", "pjds", 64, "block", 256),
+    Config("pjds_b64_w1024", "pjds", 64, "block", 1024),
+    Config("pjds_b64_w4096", "pjds", 64, "block", 4096),
+    Config("pjds_b64_w16384", "pjds", 64, "block", 16384),
+    Config("pjds_b64_w65536", "pjds", 64, "block", 65536),
+    Config("pjds_b64_w4096_xcd", "pjds", 64, "block", 4096, xcd_remap=True),
+    Config("pjds_b64_w65536_xcd", "pjds", 64, "block", 65536, xcd_remap=True),
+    Config("ellr", "ellr"),
+    Config("csr_v1", "csr", variant=1),
+    Config("csr_v4", "csr", variant=4),
+    Config("csr_v16", "csr", variant=16),
+)
+CONFIG_NAMES = tuple(c.name for c in CATALOG)
+DEFAULT = 0
+
+# ELLPACK-R is skipped when its padded storage would exceed this many bytes
+ELLR_LIMIT_BYTES = 24 * 2 ** 30
+
+
+def device_name() -> str:
+    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+
+
+def time_median(fn, reps: int = 7, warmup: int = 2) -> float:
+    """Median milliseconds of `fn` over `reps` launches, each between two events."""
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    return float(np.median([s.elapsed_time(e) for s, e in ev]))
+
+
+def _build(A, cfg: Config, device):
+    if cfg.fmt == "pjds":
+        return PjdsMatrix.from_csr(A, block_height=cfg.block_height, layout=cfg.layout,
+                                   sort_window=cfg.sort_window if cfg.sort_window < A.n_rows else 0,
+                                   split_len=cfg.split_len, device=device)
+    if cfg.fmt == "ellr":
+        info = EllrMatrix.plan(A)
+        vb = np.asarray(A.val).dtype.itemsize
+        if info.nnz_stored * (vb + 4) > ELLR_LIMIT_BYTES:
+            return None
+        return EllrMatrix.from_csr(A, device=device)
+    return CsrMatrix.from_csr(A, device=device)
+
+
+def _runner(obj, cfg: Config, x, y):
+    if cfg.fmt == "pjds":
+        return lambda: obj.spmv(x, y, y_permuted=True, xcd_remap=cfg.xcd_remap)
+    if cfg.fmt == "ellr":
+        return lambda: obj.spmv(x, y)
+    return lambda: obj.spmv(x, y, variant=cfg.variant)
+
+
+def time_all(A, x: torch.Tensor | None = None, configs=CATALOG, reps: int = 7, warmup: int = 2,
+             device="cuda") -> dict[str, float]:
+    """Median ms of y = A x for every configuration (inf where a format is not built)."""
+    dt = torch.float64 if np.asarray(A.val).dtype == np.float64 else torch.float32
+    if x is None:
+        import synth
+        x = torch.from_numpy(synth.dense_x(A.n_cols, 1)).to(device, dt)
+    y = torch.empty(A.n_rows, dtype=dt, device=device)
+    out: dict[str, float] = {}
+    groups: dict[tuple, list[Config]] = {}
+    for c in configs:
+        groups.setdefault(c.storage_key(), []).append(c)
+    for _, cfgs in groups.items():
+        obj = _build(A, cfgs[0], device)
+        for c in cfgs:
+            out[c.name] = float("inf") if obj is None else time_median(_runner(obj, c, x, y), reps, warmup)
+        del obj
+    return out
+
+
+@dataclass
+class TuneResult:
+    best: Config
+    times_ms: dict[str, float] = field(default_factory=dict)
+
+    @property
+    def speedup_over_default(self) -> float:
+        return self.times_ms[CATALOG[DEFAULT].name] / self.times_ms[self.best.name]
+
+
+def autotune(A, **kw) -> TuneResult:
+    """Exhaustive search: the fastest catalog configuration for A."""
+    t = time_all(A, **kw)
+    best = min(CATALOG, key=lambda c: t[c.name])
+    return TuneResult(best, t)
+
+
+class ResultStore:
+    """Append-only JSON-lines store of sweep records, one per (key, device)."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.records: dict[tuple[str, str], dict] = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                for line in f:
+                    line = line.strip()
+                    if line:
+                        r = json.loads(line)
+                        self.records[(r["key"], r["device"])] = r
+
+    def has(self, key: str, device: str) -> bool:
+        return (key, device) in self.records
+
+    def add(self, record: dict) -> None:
+        self.records[(record["key"], record["device"])] = record
+        with open(self.path, "a") as f:
+            f.write(json.dumps(record) + "\n")
+
+
+def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[int, dict[int, float]]:
+    """Vectors per tile for k right-hand sides: the fastest t in {1, 2, 4, 8, 16, 32}, t <= k."""
+    import synth
+    X = torch.from_numpy(synth.dense_x(M.n_cols, 4, k=k).reshape(M.n_cols, k)).to(M.device, M.dtype)
+    Y = torch.empty((M.n_rows, k), dtype=M.dtype, device=M.device)
+    t_ms = {}
+    for t in (1, 2, 4, 8, 16, 32):
+        if t > max(k, 1) * 2 or (t > 1 and t // 2 >= k):
+            continue
+        t_ms[t] = time_median(lambda: M.spmmv(X, Y, vectors_per_tile=t, y_permuted=True), reps, 1)
+    return min(t_ms, key=t_ms.get), t_ms
+
+
+def tune_batch(mats, xs, ys, groups=(1, 4, 8, 32), reps: int = 5) -> tuple[int, dict[int, float]]:
+    """Tile size (wave groups per tile) of the persistent batch launch."""
+    from .matrix import PjdsBatch
+    t_ms = {}
+    for g in groups:
+        B = PjdsBatch(mats, xs, ys, mode=L.PJDS_BATCH_PERSISTENT, y_permuted=True, groups_per_tile=g)
+        t_ms[g] = time_median(B.launch, reps, 1)
+        B.close()
+    return min(t_ms, key=t_ms.get), t_ms

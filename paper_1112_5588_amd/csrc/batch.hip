@@ -3,8 +3,8 @@
 // Three execution modes share one handle:
 //  * PJDS_BATCH_PERSISTENT: a single launch of a persistent kernel.  The rows of all members
 //    are cut into tiles of up to `groups_per_tile` wave groups (64 sorted rows each); the
-//    tiles are ordered by estimated work, longest first, and every wave pulls the next tile
-//    from one device counter until the table is exhausted (every wave then exits).  A small
+//    tiles are ordered member by member, largest member first, and every wave pulls the
+//    next tile from one device counter until the table is exhausted (every wave then exits).  A small
 //    fill kernel resets the counter in front of it.  Both kernels are captured once in a
 //    HIP graph; a launch replays it.
 //  * PJDS_BATCH_GRAPH: one pjds_spmv launch per member, captured in a HIP graph.
@@ -245,27 +245,26 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
 
     if (mode == PJDS_BATCH_PERSISTENT) {
         std::vector<Member> dm(static_cast<size_t>(n_members));
-        std::vector<Tile> tiles;
-        std::vector<double> cost;
+        // Members are visited largest first and each member's tiles stay together, so the
+        // waves running at any moment share one member's x in cache; the small members at
+        // the end fill the tail of the launch.
+        std::vector<int32_t> order(static_cast<size_t>(n_members));
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+            return members[a].info->nnz_stored > members[c].info->nnz_stored;
+        });
+        std::vector<Tile> sorted;
         for (int32_t k = 0; k < n_members; ++k) {
             const pjds_batch_member &m = members[k];
             const pjds_info &in = *m.info;
             dm[size_t(k)] = Member{m.d_row_len, m.d_offsets, m.d_col_p, m.d_val_p, m.d_perm, m.d_x, m.d_y, in.n_rows, in.n_pad};
-            const int64_t groups = ceil_div(in.n_pad, kWave);
-            const double per_group = in.n_pad ? double(in.nnz_stored) / double(in.n_pad) * kWave : 0.0;
-            for (int64_t g = 0; g < groups; g += groups_per_tile) {
-                const int64_t g1 = std::min(groups, g + groups_per_tile);
-                tiles.push_back(Tile{k, int32_t(g), int32_t(g1), 0});
-                cost.push_back(per_group * double(g1 - g));
-            }
         }
-        if (tiles.size() > size_t(INT32_MAX)) { release(b); return fail(PJDS_ERR_OVERFLOW, "too many tiles"); }
-        // longest tiles first; ties by (member, position) keep the order deterministic
-        std::vector<size_t> order(tiles.size());
-        std::iota(order.begin(), order.end(), size_t(0));
-        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
-        std::vector<Tile> sorted(tiles.size());
-        for (size_t q = 0; q < order.size(); ++q) sorted[q] = tiles[order[q]];
+        for (int32_t k : order) {
+            const int64_t groups = ceil_div(members[k].info->n_pad, kWave);
+            for (int64_t g = 0; g < groups; g += groups_per_tile)
+                sorted.push_back(Tile{k, int32_t(g), int32_t(std::min(groups, g + groups_per_tile)), 0});
+        }
+        if (sorted.size() > size_t(INT32_MAX)) { release(b); return fail(PJDS_ERR_OVERFLOW, "too many tiles"); }
         b->n_tiles = int32_t(sorted.size());
         int dev = 0, cus = 0;
         hipError_t e = hipGetDevice(&dev);

@@ -148,6 +148,8 @@ def main() -> int:
     ap.add_argument("--split-len", type=int, default=0)
     ap.add_argument("--sort-window", type=int, default=0, help="0 = global sort")
     ap.add_argument("--xcd-remap", action="store_true")
+    ap.add_argument("--x-halo", type=int, default=-1,
+                    help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip comparison legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-matrix batch leg")
@@ -191,8 +193,12 @@ def main() -> int:
     y_dev = torch.empty(n, dtype=tdt, device="cuda")
     y_perm = args.mode in ("y_permuted", "symmetric")
 
-    def step():
-        M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
+    if args.x_halo >= 0:
+        def step():
+            M.spmv_xlds(x_dev, y_dev, x_halo=args.x_halo, y_permuted=y_perm, xcd_remap=args.xcd_remap)
+    else:
+        def step():
+            M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
 
     log("timing")
     ms = time_launches(step, args.steps, args.warmup)
@@ -219,7 +225,7 @@ def main() -> int:
         import oracle
         out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
 
-    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_{args.mode}")
+    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_{args.mode}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",
         "value": round(gbs, 2),
@@ -235,11 +241,12 @@ def main() -> int:
         "data": "synthetic (seeded generator standing in for the paper's Holstein-Hubbard matrix)",
         "config": {"workload": desc, "n_rows": n, "nnz": nnz, "block_height": args.block_height,
                    "layout": args.layout, "mode": args.mode, "nnz_stored": M.info.nnz_stored,
-                   "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap,
+                   "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "pjds_spmv_kernel", "alg_bytes_per_launch": b_alg},
+                     "kernel": "pjds_spmv_lds_kernel" if args.x_halo >= 0 else "pjds_spmv_kernel",
+                     "alg_bytes_per_launch": b_alg},
         "cpu_baseline": cpu,
         "gflops": round(gflops, 2),
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
@@ -300,6 +307,25 @@ def main() -> int:
             spmmv[f"k{k}_t{t}"] = {"ms": round(ms_k, 5), "gflops": round(2 * k * nnz / ms_k / 1e6, 2)}
             del X, Y
         extra["spmmv"] = spmmv
+        # exhaustive autotuner on this matrix: every catalog configuration, plus x in LDS
+        from paper_1112_5588_amd import autotune
+        log("autotuner leg")
+        xo = torch.from_numpy(x_np).to("cuda", tdt)
+        t_cat = autotune.time_all(A, x=xo)
+        lds = {}
+        for sw, halo in ((256, 1024), (1024, 1024), (4096, 1024)):
+            Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
+            yw = torch.empty(n, dtype=tdt, device="cuda")
+            lds[f"pjds_b64_w{sw}_lds{halo}"] = autotune.time_median(
+                lambda: Mw.spmv_xlds(xo, yw, x_halo=halo, y_permuted=True), 20, 3)
+            del Mw
+        t_all = {**t_cat, **lds}
+        best = min(t_all, key=t_all.get)
+        plain = t_all[autotune.CONFIG_NAMES[autotune.DEFAULT]]
+        extra["autotune"] = {"ms": {k: round(v, 5) for k, v in t_all.items()}, "best": best,
+                             "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
+                             "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
+                             "tuned_over_plain": round(plain / t_all[best], 3)}
         result["extra"] = extra
         del M, x_dev, y_dev
         torch.cuda.empty_cache()

@@ -154,6 +154,23 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               uint32_t flags, void *stream);
 
 /*
+ * y = A x like pjds_spmv, with the right-hand side staged in LDS.  Needs the block layout and
+ * a sort window that is a multiple of 256.  Sorting never moves a row out of its window of
+ * original rows, so a workgroup owning `tile_rows` consecutive sorted rows (a multiple of 256
+ * that divides, or is divided by, the window; 0 -> max(window, 1024)) works on original rows
+ * inside the windows it touches, [lo, hi).  It copies x[lo - x_halo, hi + x_halo) (clipped to
+ * [0, n_cols)) into LDS once, then entries whose column falls in that range read x from LDS
+ * and the others from global memory.  For matrices whose non-zeros cluster near the diagonal
+ * this replaces most scattered global gathers with LDS reads (the right-hand-side reuse that
+ * eq. (1) calls alpha).  The staged range, (max(tile_rows, window) + 2*x_halo) values, must
+ * fit 64 KiB; ERR_ARG otherwise.  Rows are not split (no schedule or workspace).
+ */
+int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                   const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm, int32_t dtype,
+                   const void *d_x, void *d_y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
+                   void *stream);
+
+/*
  * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v]
  * (Y in the permuted row order with PJDS_Y_PERMUTED).  t = vectors_per_tile (1, 2, 4, 8,
  * 16 or 32) consecutive lanes share one row, each applying the row's entries to one of t

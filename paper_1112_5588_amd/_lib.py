@@ -80,6 +80,7 @@ _SIGS = {
     "pjds_workspace_init": [_ip, _i32, _vp, _vp],
     "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "ellr_plan": [_i64, _i64, _vp, _ip],
     "ellr_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -209,6 +210,13 @@ def pjds_spmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d
                            _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
                            _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), flags, _stream(stream)),
            "pjds_spmv")
+
+
+def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
+                   x_halo: int, tile_rows: int = 0, flags: int = 0, stream=None) -> None:
+    _check(lib().pjds_spmv_xlds(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                                _dev(d_val_p), _dev(d_perm), _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y),
+                                x_halo, tile_rows, flags, _stream(stream)), "pjds_spmv_xlds")
 
 
 def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,

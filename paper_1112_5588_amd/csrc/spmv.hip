@@ -78,15 +78,33 @@ struct EllrAddr {                       // ELLPACK-R: j * n_pad + i
     __device__ int64_t operator()(int j, int64_t b) const { return int64_t(j) * n_pad + b; }
 };
 
+// Reads of the right-hand side: x[c * ld + off] through the caches ...
+template <class T>
+struct XGlobal {
+    const T *__restrict__ x;
+    int64_t ld, off;
+    __device__ T operator()(int32_t c) const { return x[int64_t(c) * ld + off]; }
+};
+// ... or, for columns inside the window [lo, lo + n) staged in LDS, from LDS.
+template <class T>
+struct XStaged {
+    const T *__restrict__ x;
+    const T *lds;
+    int64_t lo;
+    uint32_t n;
+    __device__ T operator()(int32_t c) const {
+        const uint32_t d = uint32_t(int64_t(c) - lo);
+        return d < n ? lds[d] : x[c];
+    }
+};
+
 // U consecutive entries j in [jb, jb+U) (all below the wave's longest row) added into acc:
 // U independent value/index loads, then U gathers, then U FMAs.  A lane past the end of its
 // row reads the lead row's slot (an entry that exists for every such j) and keeps acc.
-// The gather reads X[c * ldx + xoff] (ldx = 1, xoff = 0 for a single vector).
-template <int U, class T, class Addr>
+template <int U, class T, class Addr, class XR>
 __device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base, int64_t base_lead,
                                           const Addr &addr, const int32_t *__restrict__ col_p,
-                                          const T *__restrict__ val_p, const T *__restrict__ x,
-                                          int64_t ldx, int64_t xoff) {
+                                          const T *__restrict__ val_p, const XR &xr) {
     T v[U];
     int32_t c[U];
 #pragma unroll
@@ -98,7 +116,7 @@ __device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base,
     }
     T xv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = x[int64_t(c[u]) * ldx + xoff];
+    for (int u = 0; u < U; ++u) xv[u] = xr(c[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const T s = __builtin_fma(v[u], xv[u], acc);
@@ -109,29 +127,28 @@ __device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base,
 // Sum of the calling lane's row entries j in [j0, j1) (Listing 1 / Listing 2 inner loop).
 // j1 is wave-uniform and <= the wave's longest row, which is row i_lead.  Full groups of
 // kUnroll steps, then an 8/4/2/1 tail, so no load is issued past j1.
-template <class T, class Addr>
+template <class T, class Addr, class XR>
 __device__ __forceinline__ T row_range_sum(int64_t i, int64_t i_lead, int len, int j0, int j1,
                                            const Addr &addr, const int32_t *__restrict__ col_p,
-                                           const T *__restrict__ val_p, const T *__restrict__ x,
-                                           int64_t ldx = 1, int64_t xoff = 0) {
+                                           const T *__restrict__ val_p, const XR &xr) {
     const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
     T acc = T(0);
     int jb = j0;
     for (; jb + kUnroll <= j1; jb += kUnroll)
-        row_steps<kUnroll>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        row_steps<kUnroll>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
     if (kUnroll > 8 && jb + 8 <= j1) {
-        row_steps<8>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        row_steps<8>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
         jb += 8;
     }
     if (kUnroll > 4 && jb + 4 <= j1) {
-        row_steps<4>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        row_steps<4>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
         jb += 4;
     }
     if (kUnroll > 2 && jb + 2 <= j1) {
-        row_steps<2>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+        row_steps<2>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
         jb += 2;
     }
-    if (jb < j1) row_steps<1>(acc, jb, len, base, base_lead, addr, col_p, val_p, x, ldx, xoff);
+    if (jb < j1) row_steps<1>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
     return acc;
 }
 
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
         const int m = wave_max(len);
         const int64_t i_lead = i - lane + lead_lane(len, m);
         const int j0 = c * split_len, j1 = min(j0 + split_len, m);
-        const T part = row_range_sum(i, i_lead, len, j0, j1, PjdsAddr<JD, BR>{offsets}, col_p, val_p, x);
+        const T part = row_range_sum(i, i_lead, len, j0, j1, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{x, 1, 0});
         partials[w * kWave + lane] = part;
         __threadfence();                                    // publish the partial sums
         int last = 0;
@@ -178,8 +195,47 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     const int m = wave_max(len);
     if (split_len > 0 && m > split_len) return;            // done by the work items above
     const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : i;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, x);
+    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{x, 1, 0});
     if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
+}
+
+// pJDS product with the right-hand side staged in LDS (block layout with a sort window).
+// A workgroup (4 waves) owns `tile` consecutive sorted rows (a multiple of 256).  Sorting
+// never moves a row out of its window of `window` original rows, so the tile's rows are
+// original rows inside [lo_r, hi_r), the union of the windows the tile touches.  The
+// workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into LDS once with
+// coalesced loads, then runs its rows 256 at a time; entries whose column falls in the staged
+// range read x from LDS, the others from global memory.  Rows are never split here.  Same
+// arithmetic order as pjds_spmv_kernel.
+template <class T, int BR>
+__global__ __launch_bounds__(kBlock) void pjds_spmv_lds_kernel(
+    int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
+    const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+    const int32_t *__restrict__ perm, const T *__restrict__ x, T *__restrict__ y, uint32_t flags) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *xs = reinterpret_cast<T *>(lds_raw);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r0 = int64_t(logical_block(flags)) * tile;         // first sorted row of the tile
+    const int64_t lo_r = r0 / window * window;
+    const int64_t hi_r = (r0 + tile + window - 1) / window * window;
+    const int64_t lo = lo_r - halo > 0 ? lo_r - halo : 0;
+    const int64_t hi = hi_r + halo < n_cols ? hi_r + halo : n_cols;
+    for (int64_t c = lo + threadIdx.x; c < hi; c += kBlock) xs[c - lo] = x[c];
+    __syncthreads();
+    const XStaged<T> xr{x, xs, lo, uint32_t(hi > lo ? hi - lo : 0)};
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+    for (int64_t rb = r0; rb < r0 + tile && rb < n_pad; rb += kBlock) {
+        const int64_t i = rb + threadIdx.x;
+        const int len = i < n_pad ? row_len[i] : 0;
+        const int m = wave_max(len);
+        // rows past n_pad (length 0) address the last real row, so the block offsets are
+        // never read out of range
+        const int64_t ia = i < n_pad ? i : n_pad - 1;
+        const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : ia;
+        const T acc = row_range_sum(ia, i_lead, len, 0, m, PjdsAddr<false, BR>{offsets}, col_p, val_p, xr);
+        if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
+    }
 }
 
 __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
@@ -212,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
         return;
     }
     const int64_t i_lead = w * R + lead_lane(len, m) / LPR;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, X, k, vc);
+    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{X, k, vc});
     if (i < n_rows && v < k) Y[int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v] = acc;
 }
 
@@ -227,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void ellr_spmv_kernel(
     const int m = wave_max(len);
     // lanes past their row read the slot of the wave's longest row (never padding)
     const int64_t i_lead = m > 0 ? i - (threadIdx.x & (kWave - 1)) + lead_lane(len, m) : 0;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, EllrAddr{n_pad}, col_e, val_e, x);
+    const T acc = row_range_sum(i, i_lead, len, 0, m, EllrAddr{n_pad}, col_e, val_e, XGlobal<T>{x, 1, 0});
     if (i < n_rows) y[i] = acc;
 }
 
@@ -442,6 +498,47 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
                      d_offsets, d_col_p, d_val_p, d_perm, k, t, d_X, d_Y, flags,
                      static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmmv");
+}
+
+int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                   const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm, int32_t dtype,
+                   const void *d_x, void *d_y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
+                   void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    const int64_t w = info->sort_window;
+    if (!(info->flags & PJDS_LAYOUT_BLOCK) || w >= info->n_rows || w % kBlock)
+        return fail(PJDS_ERR_ARG, "x staging needs the block layout and a sort window that is a multiple of %d", kBlock);
+    if (x_halo < 0) return fail(PJDS_ERR_ARG, "x_halo %d", x_halo);
+    const int64_t tile = tile_rows == 0 ? std::max<int64_t>(w, 1024) : tile_rows;
+    if (tile < kBlock || tile % kBlock || (tile % w && w % tile))
+        return fail(PJDS_ERR_ARG, "tile_rows %lld: a multiple of %d that divides or is divided by the sort window", (long long)tile, kBlock);
+    const int64_t tsize = dtype == PJDS_F64 ? 8 : 4;
+    const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), info->n_cols);
+    if (cap * tsize > 64 * 1024) return fail(PJDS_ERR_ARG, "x range of %lld entries exceeds 64 KiB of LDS", (long long)cap);
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
+    const dim3 grid(unsigned(ceil_div(info->n_pad, tile)));
+    const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        const int br = info->block_height;
+#define PJDS_XLDS_CASE(B)                                                                                \
+        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B>), grid, dim3(kBlock), lds, s, info->n_rows, info->n_cols, \
+                           info->n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,              \
+                           static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
+                           static_cast<T *>(d_y), flags)
+        if (br == 32) PJDS_XLDS_CASE(32);
+        else if (br == 64) PJDS_XLDS_CASE(64);
+        else PJDS_XLDS_CASE(128);
+#undef PJDS_XLDS_CASE
+    };
+    if (dtype == PJDS_F64) go(double{});
+    else go(float{});
+    return launch_status("pjds_spmv_xlds");
 }
 
 int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_col_e,

@@ -242,3 +242,45 @@ def test_powerlaw_full_size_sampled():
     ref = oracle.csr_spmv(sampled_rows(A, rows), x)
     assert oracle.rel_l2(y[rows], ref) <= 1e-12
     assert np.array_equal(host(M.spmv(dev(x))), y)
+
+
+# ------------------------------------------------------------------ x staged in LDS
+
+@pytest.mark.parametrize("b_r,window,halo,tile", [(64, 256, 1024, 0), (64, 1024, 512, 256), (32, 256, 0, 2048),
+                                                  (128, 4096, 2048, 1024), (64, 512, 3000, 512), (64, 256, 512, 1024)])
+@pytest.mark.parametrize("y_permuted", [False, True])
+def test_xlds_matches_oracle_and_plain_kernel(b_r, window, halo, tile, y_permuted):
+    # 9501 rows (ragged last workgroup), band plus far off-diagonals: some columns in the
+    # staged window, some outside
+    A = synth.hh_like(9501, seed=23, band=600)
+    x = synth.dense_x(A.n_cols, 23)
+    M = PjdsMatrix.from_csr(A, block_height=b_r, layout="block", sort_window=window, keep_host=True)
+    xd = dev(x)
+    y = host(M.spmv_xlds(xd, x_halo=halo, tile_rows=tile, y_permuted=y_permuted))
+    ref = oracle.csr_spmv(A, x)
+    if y_permuted:
+        ref = ref[M.host["perm"]]
+    assert oracle.rel_l2(y, ref) <= 1e-12
+    # the same values reach the same FMAs in the same order: bit-identical to the plain kernel
+    assert np.array_equal(y, host(M.spmv(xd, y_permuted=y_permuted)))
+
+
+def test_xlds_float32_rectangular_and_wide_rows():
+    A = synth.random_csr(5000, 3000, 29, max_len=60).astype(np.float32)
+    x = synth.dense_x(3000, 29).astype(np.float32).astype(np.float64)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=1024)
+    y = host(M.spmv_xlds(dev(x, torch.float32), x_halo=2048))
+    assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-5
+
+
+def test_xlds_rejects_unsupported_layouts():
+    A = synth.random_csr(20000, 20000, 30, max_len=10)
+    xd = dev(synth.dense_x(20000, 30))
+    with pytest.raises(L.PjdsError):
+        PjdsMatrix.from_csr(A, layout="jd").spmv_xlds(xd)
+    with pytest.raises(L.PjdsError):
+        PjdsMatrix.from_csr(A, layout="block", sort_window=64).spmv_xlds(xd)       # not a multiple of 256
+    with pytest.raises(L.PjdsError):
+        PjdsMatrix.from_csr(A, layout="block", sort_window=1024).spmv_xlds(xd, x_halo=4000)  # > 64 KiB
+    with pytest.raises(L.PjdsError):
+        PjdsMatrix.from_csr(A, layout="block", sort_window=1024).spmv_xlds(xd, tile_rows=768)  # 768 vs 1024

@@ -2,9 +2,12 @@
 """Benchmark: pJDS sparse matrix-vector product on one MI355X.
 
 Default workload: the Holstein-Hubbard-like matrix (N = 2^22 rows, banded symmetric pattern
-with contiguous off-diagonals, row lengths 5..20, N(0,1) values), FP64, block height 64,
-jagged-diagonal layout, y written in the permuted basis (the paper's Listing 2).  One step
-is one product y = A x with the matrix and x already resident in HBM.
+with contiguous off-diagonals, row lengths 5..20, N(0,1) values), FP64.  Default kernel
+configuration: the tuned pJDS form -- block height 64, rows sorted inside windows of 256
+(per-block layout), x staged in LDS per 512-row tile with a halo of 512, y written in the
+permuted basis (Listing 2).  The paper's plain configuration (global sort, jagged-diagonal
+layout) is timed beside it in `extra.autotune`.  One step is one product y = A x with the
+matrix and x already resident in HBM.
 
 Prints ONE JSON line.  `value` is the achieved bandwidth by the algorithmic byte count of
 the product, 12 B per non-zero (value + column index) plus 8 B per row for x and 8 B per
@@ -143,13 +146,14 @@ def main() -> int:
     ap.add_argument("--workload", default="hh_like", choices=["hh_like", "laplacian", "powerlaw"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--block-height", type=int, default=64)
-    ap.add_argument("--layout", default="jd", choices=["jd", "block"])
+    ap.add_argument("--layout", default="block", choices=["jd", "block"])
     ap.add_argument("--mode", default="y_permuted", choices=["y_permuted", "scatter", "symmetric"])
     ap.add_argument("--split-len", type=int, default=0)
-    ap.add_argument("--sort-window", type=int, default=0, help="0 = global sort")
+    ap.add_argument("--sort-window", type=int, default=256, help="0 = global sort")
     ap.add_argument("--xcd-remap", action="store_true")
-    ap.add_argument("--x-halo", type=int, default=-1,
-                    help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0)")
+    ap.add_argument("--x-halo", type=int, default=512,
+                    help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0); -1: x through the caches")
+    ap.add_argument("--tile-rows", type=int, default=512, help="rows per workgroup of the LDS path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip comparison legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-matrix batch leg")
@@ -195,7 +199,8 @@ def main() -> int:
 
     if args.x_halo >= 0:
         def step():
-            M.spmv_xlds(x_dev, y_dev, x_halo=args.x_halo, y_permuted=y_perm, xcd_remap=args.xcd_remap)
+            M.spmv_xlds(x_dev, y_dev, x_halo=args.x_halo, tile_rows=args.tile_rows, y_permuted=y_perm,
+                        xcd_remap=args.xcd_remap)
     else:
         def step():
             M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
@@ -225,7 +230,7 @@ def main() -> int:
         import oracle
         out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
 
-    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_{args.mode}")
+    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_t{args.tile_rows}_{args.mode}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",
         "value": round(gbs, 2),
@@ -242,6 +247,7 @@ def main() -> int:
         "config": {"workload": desc, "n_rows": n, "nnz": nnz, "block_height": args.block_height,
                    "layout": args.layout, "mode": args.mode, "nnz_stored": M.info.nnz_stored,
                    "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
+                   "tile_rows": args.tile_rows if args.x_halo >= 0 else None,
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -313,11 +319,11 @@ def main() -> int:
         xo = torch.from_numpy(x_np).to("cuda", tdt)
         t_cat = autotune.time_all(A, x=xo)
         lds = {}
-        for sw, halo in ((256, 1024), (1024, 1024), (4096, 1024)):
+        for sw, halo, tile in ((256, 512, 512), (512, 1024, 512), (1024, 1024, 1024)):
             Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
             yw = torch.empty(n, dtype=tdt, device="cuda")
-            lds[f"pjds_b64_w{sw}_lds{halo}"] = autotune.time_median(
-                lambda: Mw.spmv_xlds(xo, yw, x_halo=halo, y_permuted=True), 20, 3)
+            lds[f"pjds_b64_w{sw}_lds{halo}_t{tile}"] = autotune.time_median(
+                lambda: Mw.spmv_xlds(xo, yw, x_halo=halo, tile_rows=tile, y_permuted=True), 20, 3)
             del Mw
         t_all = {**t_cat, **lds}
         best = min(t_all, key=t_all.get)

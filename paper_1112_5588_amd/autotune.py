@@ -3,7 +3,7 @@
 For a matrix it converts once per distinct storage (format, block height, sort window,
 layout, long-row split), times every catalog entry that uses it (median of `reps`
 launches, each bracketed by HIP events on the launch stream, after `warmup` launches), and
-returns the fastest.  It is the reference the learned tuner is judged against (regret 0 by
+returns the fastest.  It is the reference the learned tuner is compared with (regret 0 by
 definition) and its fallback.
 
 Results can be appended to a JSON-lines store keyed by (matrix key, configuration,

@@ -106,35 +106,41 @@ def cpu_baseline(A, x, budget_s: float = 12.0):
 def batch_leg(torch) -> dict:
     """512 uneven matrices (rows log-uniform in [1e3, 5e5], 3..60 entries per row, columns
     within +-4096 of the diagonal), FP64: one persistent launch in a HIP graph vs one launch
-    per member captured in a graph vs one launch per member issued directly."""
+    per member captured in a graph vs one launch per member issued directly; members stored
+    with a global sort (JD layout) and with a 256-row sort window (block layout)."""
     import synth
     from synth import torchgen
     from paper_1112_5588_amd import PjdsBatch, PjdsMatrix, _lib
-    log("batch: generating and converting 512 matrices")
-    t0 = time.perf_counter()
     sizes = synth.uneven_batch_sizes(512)
-    mats, xs, ys = [], [], []
-    for m, n in enumerate(sizes):
-        rp, col, val = torchgen.banded_stratified(int(n), 1000 + m, device="cuda")
-        mats.append(PjdsMatrix.from_arrays(int(n), int(n), rp, col, val, split_len=-1))
-        xs.append(torchgen.dense_x(int(n), 1000 + m, device="cuda"))
-        ys.append(torch.empty(int(n), dtype=torch.float64, device="cuda"))
-        del rp, col, val
-    t_setup = time.perf_counter() - t0
-    nnz = sum(M.info.nnz for M in mats)
-    rows = int(sizes.sum())
-    b_alg = 12 * nnz + 16 * rows
-    out = {"workload": "512 matrices, rows log-uniform in [1e3, 5e5], 3..60 entries per row within +-4096 of the diagonal, U[-1,1) FP64, seeds 1000+m",
-           "rows": rows, "nnz": nnz, "setup_s": round(t_setup, 1)}
-    log(f"batch: {rows} rows, {nnz} non-zeros, setup {t_setup:.1f}s; timing")
-    for name, mode in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT), ("per_member_graph", _lib.PJDS_BATCH_GRAPH),
-                       ("direct_launches", _lib.PJDS_BATCH_DIRECT)):
-        B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True)
-        ms = time_launches(B.launch, 10, 2)
-        out[name] = {"ms": round(ms, 4), "gflops": round(2 * nnz / ms / 1e6, 1), "GBps_alg": round(b_alg / ms / 1e6, 1)}
-        if mode == _lib.PJDS_BATCH_PERSISTENT:
-            out[name]["tiles"], out[name]["grid"] = B.info()
-        B.close()
+    out = {"workload": "512 matrices, rows log-uniform in [1e3, 5e5], 3..60 entries per row within +-4096 of the diagonal, U[-1,1) FP64, seeds 1000+m"}
+    for label, kw in (("global_sort", dict(layout="jd")), ("window256", dict(layout="block", sort_window=256))):
+        log(f"batch ({label}): generating and converting 512 matrices")
+        t0 = time.perf_counter()
+        mats, xs, ys = [], [], []
+        for m, n in enumerate(sizes):
+            rp, col, val = torchgen.banded_stratified(int(n), 1000 + m, device="cuda")
+            mats.append(PjdsMatrix.from_arrays(int(n), int(n), rp, col, val, split_len=-1,
+                                               **(kw if kw.get("sort_window", 0) < n else dict(layout=kw["layout"]))))
+            xs.append(torchgen.dense_x(int(n), 1000 + m, device="cuda"))
+            ys.append(torch.empty(int(n), dtype=torch.float64, device="cuda"))
+            del rp, col, val
+        t_setup = time.perf_counter() - t0
+        nnz = sum(M.info.nnz for M in mats)
+        rows = int(sizes.sum())
+        b_alg = 12 * nnz + 16 * rows
+        res = {"setup_s": round(t_setup, 1), "nnz_stored": sum(M.info.nnz_stored for M in mats)}
+        out["rows"], out["nnz"] = rows, nnz
+        for name, mode in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT), ("per_member_graph", _lib.PJDS_BATCH_GRAPH),
+                           ("direct_launches", _lib.PJDS_BATCH_DIRECT)):
+            B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True)
+            ms = time_launches(B.launch, 10, 2)
+            res[name] = {"ms": round(ms, 4), "gflops": round(2 * nnz / ms / 1e6, 1), "GBps_alg": round(b_alg / ms / 1e6, 1)}
+            if mode == _lib.PJDS_BATCH_PERSISTENT:
+                res[name]["tiles"], res[name]["grid"] = B.info()
+            B.close()
+        out[label] = res
+        del mats, xs, ys
+        torch.cuda.empty_cache()
     return out
 
 
@@ -305,12 +311,16 @@ def main() -> int:
         extra["pjds_scatter_y"] = {"ms": round(ms_s, 5)}
         extra["pjds_xcd_remap"] = {"ms": round(ms_nr, 5)}
         # many right-hand sides on the same matrix: effective GFLOP/s vs plain single-vector
-        spmmv = {}
-        for k, t in ((4, 4), (8, 8)):
+        spmmv = {"plain_gflops": round(gflops, 2)}
+        from paper_1112_5588_amd import autotune as _at
+        for k in (4, 8, 16, 32):
+            (t, vpl), _ = _at.tune_spmmv(M, k, reps=3)
             X = torch.from_numpy(synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)).to("cuda", tdt)
             Y = torch.empty((n, k), dtype=tdt, device="cuda")
-            ms_k = time_launches(lambda: M.spmmv(X, Y, vectors_per_tile=t, y_permuted=True), 20, 3)
-            spmmv[f"k{k}_t{t}"] = {"ms": round(ms_k, 5), "gflops": round(2 * k * nnz / ms_k / 1e6, 2)}
+            ms_k = time_launches(lambda: M.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True), 20, 3)
+            spmmv[f"k{k}"] = {"tile": t, "vectors_per_lane": vpl, "ms": round(ms_k, 5),
+                              "gflops": round(2 * k * nnz / ms_k / 1e6, 2),
+                              "over_plain": round(2 * k * nnz / ms_k / 1e6 / gflops, 2)}
             del X, Y
         extra["spmmv"] = spmmv
         # exhaustive autotuner on this matrix: every catalog configuration, plus x in LDS

@@ -172,16 +172,18 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
 
 /*
  * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v]
- * (Y in the permuted row order with PJDS_Y_PERMUTED).  t = vectors_per_tile (1, 2, 4, 8,
- * 16 or 32) consecutive lanes share one row, each applying the row's entries to one of t
- * consecutive right-hand sides; a matrix entry is loaded once per tile of t vectors, so
- * the matrix is streamed ceil(k / t) times and each gather reads t contiguous X values.
- * Arguments as pjds_spmv; k >= 1; long rows are not split (no workspace needed).
+ * (Y in the permuted row order with PJDS_Y_PERMUTED).  A tile of t = vectors_per_tile
+ * consecutive right-hand sides is handled by t / vectors_per_lane lanes per row (1, 2, 4, 8,
+ * 16 or 32), each applying the row's entries to vectors_per_lane (1, 2 or 4) adjacent
+ * right-hand sides with one wide load; a matrix entry is loaded once per tile, so the matrix
+ * is streamed ceil(k / t) times.  k must be a multiple of vectors_per_lane, and X and Y
+ * aligned to vectors_per_lane values.  Arguments otherwise as pjds_spmv; long rows are not
+ * split (no workspace needed).
  */
 int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
-               int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
-               uint32_t flags, void *stream);
+               int32_t dtype, int32_t k, int32_t vectors_per_tile, int32_t vectors_per_lane,
+               const void *d_X, void *d_Y, uint32_t flags, void *stream);
 
 /* ---- many matrices in one call ------------------------------------------------------ */
 /*

@@ -79,7 +79,7 @@ _SIGS = {
     "pjds_workspace_size": [_ip, _i32, ctypes.POINTER(ctypes.c_int64)],
     "pjds_workspace_init": [_ip, _i32, _vp, _vp],
     "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
-    "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "ellr_plan": [_i64, _i64, _vp, _ip],
     "ellr_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -220,11 +220,12 @@ def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_pe
 
 
 def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,
-               vectors_per_tile: int, d_X, d_Y, flags: int = 0, stream=None) -> None:
+               vectors_per_tile: int, d_X, d_Y, flags: int = 0, stream=None,
+               vectors_per_lane: int = 1) -> None:
     _check(lib().pjds_spmmv(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                             _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
-                            vectors_per_tile, _dev(d_X), _dev(d_Y), flags, _stream(stream)),
-           "pjds_spmmv")
+                            vectors_per_tile, vectors_per_lane, _dev(d_X), _dev(d_Y), flags,
+                            _stream(stream)), "pjds_spmmv")
 
 
 def ellr_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray) -> pjds_info:

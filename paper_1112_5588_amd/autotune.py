@@ -164,16 +164,22 @@ class ResultStore:
             f.write(json.dumps(record) + "\n")
 
 
-def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[int, dict[int, float]]:
-    """Vectors per tile for k right-hand sides: the fastest t in {1, 2, 4, 8, 16, 32}, t <= k."""
+def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[tuple[int, int], dict[tuple[int, int], float]]:
+    """(vectors per tile, vectors per lane) for k right-hand sides: the fastest pair with a
+    tile of at most 2k vectors."""
     import synth
     X = torch.from_numpy(synth.dense_x(M.n_cols, 4, k=k).reshape(M.n_cols, k)).to(M.device, M.dtype)
     Y = torch.empty((M.n_rows, k), dtype=M.dtype, device=M.device)
     t_ms = {}
-    for t in (1, 2, 4, 8, 16, 32):
-        if t > max(k, 1) * 2 or (t > 1 and t // 2 >= k):
+    for vpl in (1, 2, 4):
+        if k % vpl:
             continue
-        t_ms[t] = time_median(lambda: M.spmmv(X, Y, vectors_per_tile=t, y_permuted=True), reps, 1)
+        for lpr in (1, 2, 4, 8, 16, 32):
+            t = lpr * vpl
+            if t > 1 and t // 2 >= k:
+                continue
+            t_ms[(t, vpl)] = time_median(
+                lambda: M.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True), reps, 1)
     return min(t_ms, key=t_ms.get), t_ms
 
 

@@ -243,33 +243,77 @@ __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
 }
 
 // ---- pJDS with k right-hand sides -----------------------------------------------------
-// LPR consecutive lanes share one sorted row and each takes one right-hand side of the
-// current tile of LPR vectors: the matrix entry is loaded once for the whole tile, and the
-// LPR lanes gather LPR consecutive doubles of one row of the interleaved X (X[c*k + v]),
-// so a gather instruction touches about 64/LPR cache lines instead of 64.  A wave covers
-// R = 64/LPR consecutive sorted rows; tiles over k run in gridDim.y.
-template <class T, bool JD, int BR, int LPR>
+// A tile covers LPR * VPL consecutive right-hand sides.  LPR consecutive lanes share one
+// sorted row; each of them applies the row's entries to VPL adjacent right-hand sides, read
+// from the interleaved X (X[c*k + v]) with one VPL-wide load.  A matrix entry is therefore
+// loaded once per tile, a wave covers R = 64/LPR rows, and a gather instruction reads LPR *
+// VPL contiguous values per row.  Tiles over k run in gridDim.y.
+template <class T, int VPL>
+struct VecOf;
+template <class T>
+struct VecOf<T, 1> { typedef T type; };
+template <>
+struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <>
+struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <>
+struct VecOf<double, 4> { typedef double type __attribute__((ext_vector_type(4))); };
+template <>
+struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <class T, bool JD, int BR, int LPR, int VPL>
 __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
     int64_t n_rows, int64_t n_pad, int64_t n_waves, int32_t k,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
     const int32_t *__restrict__ perm, const T *__restrict__ X, T *__restrict__ Y, uint32_t flags) {
+    typedef typename VecOf<T, VPL>::type V;
     constexpr int R = kWave / LPR;
+    constexpr int U = VPL >= 4 ? 4 : kUnroll;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= n_waves) return;
-    const int v = int(blockIdx.y) * LPR + lane % LPR;      // this lane's right-hand side
-    const int vc = v < k ? v : k - 1;
+    // first right-hand side of this lane; k is a multiple of VPL, so a lane's VPL values are
+    // either all inside [0, k) or all outside
+    const int v = int(blockIdx.y) * (LPR * VPL) + (lane % LPR) * VPL;
+    const int vc = v < k ? v : k - VPL;
     const int64_t i = w * R + lane / LPR;
     const int len = i < n_pad ? row_len[i] : 0;
     const int m = wave_max(len);
-    if (m == 0) {
-        if (i < n_rows && v < k) Y[int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v] = T(0);
-        return;
+    V acc;
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) reinterpret_cast<T *>(&acc)[q] = T(0);
+    if (m > 0) {
+        const int64_t i_lead = w * R + lead_lane(len, m) / LPR;
+        const PjdsAddr<JD, BR> addr{offsets};
+        const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
+        for (int jb = 0; jb < m; jb += U) {
+            T a_v[U];
+            int32_t a_c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = jb + u < m ? jb + u : m - 1;      // uniform clamp past the longest row
+                const int64_t a = addr(j, j < len ? base : base_lead);
+                a_v[u] = ld_stream(val_p + a);
+                a_c[u] = ld_stream(col_p + a);
+            }
+            V xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = *reinterpret_cast<const V *>(X + int64_t(a_c[u]) * k + vc);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool on = jb + u < len && jb + u < m;
+#pragma unroll
+                for (int q = 0; q < VPL; ++q) {
+                    T &aq = reinterpret_cast<T *>(&acc)[q];
+                    const T s = __builtin_fma(a_v[u], reinterpret_cast<const T *>(&xv[u])[q], aq);
+                    aq = on ? s : aq;
+                }
+            }
+        }
     }
-    const int64_t i_lead = w * R + lead_lane(len, m) / LPR;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{X, k, vc});
-    if (i < n_rows && v < k) Y[int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v] = acc;
+    if (i < n_rows && v < k)
+        *reinterpret_cast<V *>(Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v) = acc;
 }
 
 // ---- ELLPACK-R, Listing 1 -------------------------------------------------------------
@@ -374,28 +418,39 @@ void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, con
                        static_cast<T *>(y), flags);
 }
 
+template <class T, bool JD, int BR, int LPR, int VPL>
+void launch_spmmv_lv(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
+                     const void *vp, const int32_t *perm, int32_t k, const void *X, void *Y,
+                     uint32_t flags, hipStream_t s) {
+    const int64_t waves = ceil_div(in.n_pad, kWave / LPR);
+    const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(ceil_div(k, LPR * VPL)));
+    hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL>), grid, dim3(kBlock), 0, s, in.n_rows,
+                       in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,
+                       static_cast<const T *>(X), static_cast<T *>(Y), flags);
+}
+
+template <class T, bool JD, int BR, int VPL>
+void launch_spmmv_v(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
+                    const void *vp, const int32_t *perm, int32_t k, int32_t lpr, const void *X,
+                    void *Y, uint32_t flags, hipStream_t s) {
+    switch (lpr) {
+        case 1: launch_spmmv_lv<T, JD, BR, 1, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+        case 2: launch_spmmv_lv<T, JD, BR, 2, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+        case 4: launch_spmmv_lv<T, JD, BR, 4, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+        case 8: launch_spmmv_lv<T, JD, BR, 8, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+        case 16: launch_spmmv_lv<T, JD, BR, 16, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+        default: launch_spmmv_lv<T, JD, BR, 32, VPL>(in, rl, off, cp, vp, perm, k, X, Y, flags, s); break;
+    }
+}
+
 template <class T, bool JD, int BR>
 void launch_spmmv(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
-                  const void *vp, const int32_t *perm, int32_t k, int32_t t, const void *X,
+                  const void *vp, const int32_t *perm, int32_t k, int32_t t, int32_t vpl, const void *X,
                   void *Y, uint32_t flags, hipStream_t s) {
-#define PJDS_SPMMV_CASE(TT)                                                                           \
-    case TT: {                                                                                        \
-        const int64_t waves = ceil_div(in.n_pad, kWave / TT);                                        \
-        const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(ceil_div(k, TT)));       \
-        hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, TT>), grid, dim3(kBlock), 0, s, in.n_rows,  \
-                           in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,         \
-                           static_cast<const T *>(X), static_cast<T *>(Y), flags);                    \
-        break;                                                                                        \
-    }
-    switch (t) {
-        PJDS_SPMMV_CASE(1)
-        PJDS_SPMMV_CASE(2)
-        PJDS_SPMMV_CASE(4)
-        PJDS_SPMMV_CASE(8)
-        PJDS_SPMMV_CASE(16)
-        PJDS_SPMMV_CASE(32)
-    }
-#undef PJDS_SPMMV_CASE
+    const int32_t lpr = t / vpl;
+    if (vpl == 1) launch_spmmv_v<T, JD, BR, 1>(in, rl, off, cp, vp, perm, k, lpr, X, Y, flags, s);
+    else if (vpl == 2) launch_spmmv_v<T, JD, BR, 2>(in, rl, off, cp, vp, perm, k, lpr, X, Y, flags, s);
+    else launch_spmmv_v<T, JD, BR, 4>(in, rl, off, cp, vp, perm, k, lpr, X, Y, flags, s);
 }
 
 // Dispatch on (dtype, layout, block height) to a compile-time instantiation.
@@ -481,21 +536,27 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
 
 int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
-               int32_t dtype, int32_t k, int32_t vectors_per_tile, const void *d_X, void *d_Y,
-               uint32_t flags, void *stream) {
+               int32_t dtype, int32_t k, int32_t vectors_per_tile, int32_t vectors_per_lane,
+               const void *d_X, void *d_Y, uint32_t flags, void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
     if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
     if (k < 1) return fail(PJDS_ERR_ARG, "k = %d", k);
-    const int32_t t = vectors_per_tile;
-    if (t != 1 && t != 2 && t != 4 && t != 8 && t != 16 && t != 32)
-        return fail(PJDS_ERR_ARG, "vectors_per_tile %d: must be 1, 2, 4, 8, 16 or 32", t);
+    const int32_t t = vectors_per_tile, vpl = vectors_per_lane;
+    if (vpl != 1 && vpl != 2 && vpl != 4) return fail(PJDS_ERR_ARG, "vectors_per_lane %d: must be 1, 2 or 4", vpl);
+    if (k % vpl) return fail(PJDS_ERR_ARG, "k = %d must be a multiple of vectors_per_lane %d", k, vpl);
+    const int32_t lpr = vpl ? t / vpl : 0;
+    if (t % vpl || (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32))
+        return fail(PJDS_ERR_ARG, "vectors_per_tile %d: vectors_per_lane times 1, 2, 4, 8, 16 or 32", t);
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_Y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_X)) return fail(PJDS_ERR_ARG, "NULL device array");
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter Y)");
+    const int64_t elt = dtype == PJDS_F64 ? 8 : 4;
+    if ((reinterpret_cast<uintptr_t>(d_X) | reinterpret_cast<uintptr_t>(d_Y)) % uintptr_t(elt * vpl))
+        return fail(PJDS_ERR_ARG, "X and Y must be aligned to vectors_per_lane values");
     if (ceil_div(k, t) > 65535) return fail(PJDS_ERR_ARG, "too many vector tiles");
     dispatch<SpmmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
-                     d_offsets, d_col_p, d_val_p, d_perm, k, t, d_X, d_Y, flags,
+                     d_offsets, d_col_p, d_val_p, d_perm, k, t, vpl, d_X, d_Y, flags,
                      static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmmv");
 }

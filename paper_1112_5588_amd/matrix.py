@@ -104,16 +104,18 @@ class PjdsMatrix:
         return y
 
     def spmmv(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int | None = None,
-              y_permuted: bool = False, stream=None) -> torch.Tensor:
+              y_permuted: bool = False, stream=None, vectors_per_lane: int | None = None) -> torch.Tensor:
         k = X.shape[1]
         if vectors_per_tile is None:
             vectors_per_tile = min(32, 1 << (k - 1).bit_length())
+        if vectors_per_lane is None:
+            vectors_per_lane = next(v for v in (4, 2, 1) if k % v == 0 and vectors_per_tile % v == 0)
         if Y is None:
             Y = torch.empty((self.info.n_rows, k), dtype=self.dtype, device=self.device)
         flags = L.PJDS_Y_PERMUTED if y_permuted else 0
         d = self.d
         L.pjds_spmmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], k,
-                     vectors_per_tile, X, Y, flags, stream)
+                     vectors_per_tile, X, Y, flags, stream, vectors_per_lane)
         return Y
 
     def footprint_bytes(self) -> int:

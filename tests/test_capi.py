@@ -141,7 +141,8 @@ def test_device_entry_points_validate_before_touching_the_gpu():
     assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0, None) == L.PJDS_ERR_ARG
     assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 7, None, None, 0, None) == L.PJDS_ERR_ARG
     assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0x100, None) == L.PJDS_ERR_ARG
-    assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 3, None, None, 0, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 3, 1, None, None, 0, None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 6, 8, 4, None, None, 0, None) == L.PJDS_ERR_ARG
     assert lib.csr_spmv(10, 10, None, None, None, 0, None, None, 5, None) == L.PJDS_ERR_ARG
     assert lib.pjds_probe(3, None, None, 10, None) == L.PJDS_ERR_ARG
 

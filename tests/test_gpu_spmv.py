@@ -172,15 +172,37 @@ def test_csr_parity(dtype, variant):
 
 @pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 32])
 @pytest.mark.parametrize("t", [1, 2, 4, 8, 16, 32])
-def test_spmmv_config1(k, t):
+@pytest.mark.parametrize("vpl", [1, 2, 4])
+def test_spmmv_config1(k, t, vpl):
+    if k % vpl or t % vpl:
+        pytest.skip("k and the tile must be multiples of the vectors per lane")
     A = synth.laplacian_2d(128)
     X = synth.dense_x(A.n_cols, 40, k=k).reshape(A.n_cols, k)
     M = PjdsMatrix.from_csr(A)
-    Y = host(M.spmmv(dev(X), vectors_per_tile=t))
+    Y = host(M.spmmv(dev(X), vectors_per_tile=t, vectors_per_lane=vpl))
     ref = oracle.csr_spmmv(A, X)
     assert oracle.rel_l2(Y, ref) <= 1e-12
     if k == 1:
         assert np.array_equal(Y[:, 0], host(M.spmv(dev(X[:, 0]))))
+
+
+@pytest.mark.parametrize("b_r,layout,k,t,vpl", [(32, "block", 8, 8, 2), (64, "jd", 12, 16, 4), (128, "block", 6, 4, 2)])
+def test_spmmv_wide_lanes_ragged_tiles(b_r, layout, k, t, vpl):
+    # k not a multiple of the tile: the last tile is partly outside [0, k)
+    A = synth.random_csr(9501, 7000, 19, max_len=45).astype(np.float64)
+    X = synth.dense_x(7000, 43, k=k).reshape(7000, k)
+    M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, sort_window=1024 if layout == "block" else 0)
+    Y = host(M.spmmv(dev(X), vectors_per_tile=t, vectors_per_lane=vpl))
+    assert oracle.rel_l2(Y, oracle.csr_spmmv(A, X)) <= 1e-12
+    Y32 = host(PjdsMatrix.from_csr(A.astype(np.float32)).spmmv(dev(X, torch.float32), vectors_per_tile=t, vectors_per_lane=vpl))
+    assert oracle.rel_l2(Y32, oracle.csr_spmmv(A.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))) <= 1e-5
+
+
+def test_spmmv_rejects_misaligned_lanes():
+    A = synth.laplacian_2d(32)
+    M = PjdsMatrix.from_csr(A)
+    with pytest.raises(L.PjdsError):
+        M.spmmv(dev(np.ones((A.n_cols, 6))), vectors_per_tile=8, vectors_per_lane=4)    # 6 % 4
 
 
 @pytest.mark.parametrize("b_r,layout", [(32, "jd"), (64, "block"), (128, "jd")])
@@ -189,7 +211,7 @@ def test_spmmv_random(b_r, layout):
     X = synth.dense_x(7000, 41, k=5).reshape(7000, 5)
     M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, keep_host=True)
     for yp in (False, True):
-        Y = host(M.spmmv(dev(X), vectors_per_tile=4, y_permuted=yp))
+        Y = host(M.spmmv(dev(X), vectors_per_tile=4, vectors_per_lane=1, y_permuted=yp))
         ref = oracle.csr_spmmv(A, X)
         if yp:
             ref = ref[M.host["perm"]]

@@ -338,6 +338,82 @@ def main() -> int:
         t_all = {**t_cat, **lds}
         best = min(t_all, key=t_all.get)
         plain = t_all[autotune.CONFIG_NAMES[autotune.DEFAULT]]
+        # the product inside a solver: Lanczos steps in the permuted basis (symmetric conversion)
+        if args.dtype == "f64" and A.n_rows == A.n_cols:
+            log("Lanczos leg")
+            Ms = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=256, symmetric=True)
+            v0 = torch.from_numpy(x_np).to("cuda", torch.float64)[Ms.d["perm"].long()].contiguous()
+            steps = 20
+            bufs = Ms.lanczos_buffers()
+            al = torch.empty(steps, dtype=torch.float64, device="cuda")
+            be = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+            ms_l = time_launches(lambda: Ms.lanczos(v0, steps, x_halo=512, tile_rows=512, alpha=al, beta=be,
+                                                    buffers=bufs), 5, 1)
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                with torch.cuda.graph(g, stream=cs):
+                    Ms.lanczos(v0, steps, x_halo=512, tile_rows=512, alpha=al, beta=be, buffers=bufs)
+            torch.cuda.current_stream().wait_stream(cs)
+            ms_g = time_launches(g.replay, 5, 1)
+            ys = torch.empty(n, dtype=torch.float64, device="cuda")
+            ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=512, tile_rows=512, y_permuted=True), 50, 5)
+            extra["lanczos"] = {"steps": steps, "ms_per_step_eager": round(ms_l / steps, 5),
+                                "ms_per_step_graph": round(ms_g / steps, 5), "ms_product_alone": round(ms_p, 5),
+                                "vector_passes_per_step": 8,
+                                "GBps_alg_per_step": round((b_alg + 8 * 8 * n) / (ms_g / steps) / 1e6, 1)}
+            del Ms, bufs, g
+        # host link (eq. 2-4): x to the device, the product, y back, from pinned host memory
+        xh = torch.from_numpy(x_np).to(tdt).pin_memory()
+        yh = torch.empty(n, dtype=tdt).pin_memory()
+        xd2 = torch.empty(n, dtype=tdt, device="cuda")
+
+        def h2d():
+            xd2.copy_(xh, non_blocking=True)
+
+        def d2h():
+            yh.copy_(y_dev, non_blocking=True)
+        ms_h2d = time_launches(h2d, 20, 3)
+        ms_d2h = time_launches(d2h, 20, 3)
+
+        def with_link():
+            xd2.copy_(xh, non_blocking=True)
+            step()
+            yh.copy_(y_dev, non_blocking=True)
+        ms_link = time_launches(with_link, 20, 3)
+        from paper_1112_5588_amd import model as pmodel
+        b_pci = 2 * vbytes * n / ((ms_h2d + ms_d2h) * 1e-3)
+        nnzr = nnz / n
+        extra["host_link"] = {
+            "h2d_GBps": round(vbytes * n / ms_h2d / 1e6, 1), "d2h_GBps": round(vbytes * n / ms_d2h / 1e6, 1),
+            "ms_product": round(ms, 5), "ms_with_transfers": round(ms_link, 5),
+            "transfer_share": round(1 - ms / ms_link, 4),
+            "bw_ratio_gpu_over_link": round(gbs * 1e9 / b_pci, 2),
+            "eq3_nnzr_bound_half_penalty_alpha1": round(pmodel.nnzr_bound_half_penalty(gbs * 1e9 / b_pci, 1.0), 1),
+            "eq4_nnzr_bound_tenth_penalty_alpha1": round(pmodel.nnzr_bound_tenth_penalty(gbs * 1e9 / b_pci, 1.0), 1),
+            "n_nzr": round(nnzr, 2)}
+        del xh, yh, xd2
+        # local/non-local split (vector mode with overlap): y written, then read and written again
+        from paper_1112_5588_amd.matrix import split_columns
+        loc, nl = split_columns(A, 0, A.n_cols // 2)
+        ML, MN = PjdsMatrix.from_csr(loc), PjdsMatrix.from_csr(nl)
+        M1 = PjdsMatrix.from_csr(A)
+        xo = torch.from_numpy(x_np).to("cuda", tdt)
+        yo = torch.empty(n, dtype=tdt, device="cuda")
+
+        def split_step():
+            ML.spmv(xo, yo)
+            MN.spmv_axpby(xo, yo, alpha=1.0, beta=1.0, z=yo)
+        ms_split = time_launches(split_step, 30, 3)
+        ms_one = time_launches(lambda: M1.spmv(xo, yo), 30, 3)
+        from paper_1112_5588_amd import model as pmodel
+        nnzr = nnz / n
+        extra["split_local_nonlocal"] = {
+            "ms_split": round(ms_split, 5), "ms_single": round(ms_one, 5),
+            "penalty": round(ms_split / ms_one - 1, 4),
+            "model_penalty_eq1": round((8.0 / nnzr) / pmodel.code_balance_dp(1.0 / nnzr, nnzr), 4)}
+        del ML, MN, M1
         extra["autotune"] = {"ms": {k: round(v, 5) for k, v in t_all.items()}, "best": best,
                              "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),

@@ -154,6 +154,20 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               uint32_t flags, void *stream);
 
 /*
+ * y = alpha (A x) + beta z, the product with a fused update (pjds_spmv's arguments plus
+ * alpha, beta and d_z; d_z NULL means beta is ignored).  z is indexed like y (permuted order
+ * with PJDS_Y_PERMUTED, original order otherwise) and may be y itself, which accumulates:
+ * this is how the product of a matrix split into a local and a non-local column part is
+ * assembled, y = A_local x, then y = A_nonlocal x + y (Sect. 3.1, vector mode with overlap,
+ * where the result vector is written twice).  z may not be x.
+ */
+int pjds_spmv_axpby(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                    const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+                    const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x,
+                    double alpha, double beta, const void *d_z, void *d_y, uint32_t flags,
+                    void *stream);
+
+/*
  * y = A x like pjds_spmv, with the right-hand side staged in LDS.  Needs the block layout and
  * a sort window that is a multiple of 256.  Sorting never moves a row out of its window of
  * original rows, so a workgroup owning `tile_rows` consecutive sorted rows (a multiple of 256
@@ -184,6 +198,28 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
                const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
                int32_t dtype, int32_t k, int32_t vectors_per_tile, int32_t vectors_per_lane,
                const void *d_X, void *d_Y, uint32_t flags, void *stream);
+
+/* ---- the product inside an iterative solver ----------------------------------------- */
+/*
+ * `steps` steps of the symmetric Lanczos recurrence on a square matrix converted with
+ * PJDS_SYMMETRIC, entirely in the permuted basis (the solver use of Sect. 2.1: permute once
+ * before and once after the iteration):
+ *   v_0 = v/||v||, beta_0 = 0;  w = A v_j - beta_j v_{j-1};  alpha_j = w.v_j;
+ *   w = w - alpha_j v_j;  beta_{j+1} = ||w||;  v_{j+1} = w / beta_{j+1}.
+ * FP64 only.  d_v0 [n_rows] is the start vector in the permuted basis (x_p[i] = x[perm[i]]).
+ * Outputs (device): d_alpha [steps], d_beta [steps + 1] (beta_0 = 0).  The scalars stay on the
+ * device; nothing synchronises with the host, so the call may be captured in a graph.
+ * x_halo >= 0 uses the LDS-staged product (pjds_spmv_xlds's conditions), otherwise the plain
+ * one (d_sched/d_work as for pjds_spmv).  d_vectors and d_scratch are device buffers of the
+ * sizes pjds_lanczos_workspace reports (three vectors; reduction partials).  A zero beta
+ * (invariant subspace found) makes the following steps non-finite: stop before it.
+ * Reductions use a fixed grid and fixed trees: results are reproducible bit for bit.
+ */
+int pjds_lanczos_workspace(const pjds_info *info, int64_t *vector_bytes, int64_t *scratch_bytes);
+int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                 const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
+                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, double *d_alpha,
+                 double *d_beta, void *d_vectors, void *d_scratch, void *stream);
 
 /* ---- many matrices in one call ------------------------------------------------------ */
 /*

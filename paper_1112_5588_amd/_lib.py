@@ -80,6 +80,9 @@ _SIGS = {
     "pjds_workspace_init": [_ip, _i32, _vp, _vp],
     "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmv_axpby": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _u32, _vp],
+    "pjds_lanczos_workspace": [_ip, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "ellr_plan": [_i64, _i64, _vp, _ip],
     "ellr_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -322,3 +325,27 @@ def mlp_adam_step(d_params, d_grad, d_m, d_v, step: int, lr: float = 1e-3, beta1
 def mlp_infer(d_params, d_in: int, d_out: int, d_X, d_scale, d_shift, d_valid, d_idx, d_margin, stream=None) -> None:
     _check(lib().mlp_infer(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_scale), _dev(d_shift),
                            _dev(d_valid), _dev(d_idx), _dev(d_margin), _stream(stream)), "mlp_infer")
+
+
+def pjds_spmv_axpby(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work,
+                    d_x, alpha: float, beta: float, d_z, d_y, flags: int = 0, stream=None) -> None:
+    _check(lib().pjds_spmv_axpby(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                                 _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
+                                 _dtype_code(d_y.dtype), _dev(d_x), alpha, beta, _dev(d_z), _dev(d_y),
+                                 flags, _stream(stream)), "pjds_spmv_axpby")
+
+
+def pjds_lanczos_workspace(info: pjds_info) -> tuple[int, int]:
+    a, b = _i64(0), _i64(0)
+    _check(lib().pjds_lanczos_workspace(ctypes.byref(info), ctypes.byref(a), ctypes.byref(b)),
+           "pjds_lanczos_workspace")
+    return a.value, b.value
+
+
+def pjds_lanczos(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, d_v0,
+                 steps: int, x_halo: int, tile_rows: int, d_alpha, d_beta, d_vectors, d_scratch,
+                 stream=None) -> None:
+    _check(lib().pjds_lanczos(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                              _dev(d_val_p), _dev(d_sched), _dev(d_work), _dev(d_v0), steps, x_halo,
+                              tile_rows, _dev(d_alpha), _dev(d_beta), _dev(d_vectors), _dev(d_scratch),
+                              _stream(stream)), "pjds_lanczos")

@@ -27,6 +27,14 @@ void parallel_ranges(int64_t n, F body);
 
 constexpr int kWave = 64;  // MI355X wavefront width
 
+// Type-erased form of a product's epilogue y = alpha (A x) + b z (see spmv.hip).
+struct EpiArgs {
+    double alpha = 1.0, beta = 0.0;
+    const void *z = nullptr;
+    const void *beta_dev = nullptr;   // if set, b = bscale * (*beta_dev) read on the device
+    double bscale = 0.0;
+};
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace pjds

@@ -1,0 +1,157 @@
+// The product inside an iterative solver that never leaves the permuted basis: m steps of
+// the symmetric Lanczos recurrence run entirely on the GPU.
+//
+// The paper motivates pJDS by Krylov solvers that permute once before the iteration and
+// once after it (Sect. 2.1).  With a matrix converted with PJDS_SYMMETRIC the product maps
+// permuted vectors to permuted vectors, so the whole recurrence stays in that basis:
+//
+//     w = A v_j - beta_j v_{j-1}              one pJDS product, the subtraction in its epilogue
+//     alpha_j = w . v_j                       deterministic two-stage reduction
+//     w = w - alpha_j v_j;  s = w . w         one pass
+//     beta_{j+1} = sqrt(s);  v_{j+1} = w / beta_{j+1}
+//
+// The scalars alpha and beta stay in device memory and every kernel reads them there, so a
+// step needs no host synchronisation and a sequence of steps can be captured in a graph.
+// Reductions use a fixed grid and fixed summation trees: results are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+
+#include "launch.h"
+
+namespace pjds {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 512;     // fixed, so the summation order never depends on the device
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// partial[b] = sum over this block's fixed share of a[i] * b[i]
+__global__ __launch_bounds__(kRedThreads) void dot_partial_kernel(int64_t n, const double *__restrict__ a,
+                                                                  const double *__restrict__ b,
+                                                                  double *__restrict__ partial) {
+    __shared__ double red[kRedThreads];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(kRedThreads) + threadIdx.x; i < n; i += int64_t(kRedBlocks) * kRedThreads)
+        s = __builtin_fma(a[i], b[i], s);
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// w = w - (*alpha) v, and partial[b] = this block's share of w . w (new w)
+__global__ __launch_bounds__(kRedThreads) void axpy_norm_partial_kernel(int64_t n, double *__restrict__ w,
+                                                                        const double *__restrict__ v,
+                                                                        const double *__restrict__ alpha,
+                                                                        double *__restrict__ partial) {
+    __shared__ double red[kRedThreads];
+    const double a = alpha[0];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(kRedThreads) + threadIdx.x; i < n; i += int64_t(kRedBlocks) * kRedThreads) {
+        const double wi = __builtin_fma(-a, v[i], w[i]);
+        w[i] = wi;
+        s = __builtin_fma(wi, wi, s);
+    }
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// out[0] = sum of the kRedBlocks partials (fixed tree), or its square root
+__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, double *out, int sqrt_it) {
+    __shared__ double red[kRedThreads];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < kRedBlocks; q += kRedThreads) s += partial[q];
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) out[0] = sqrt_it ? sqrt(t) : t;
+}
+
+// dst = src / (*d)   (src may be dst)
+__global__ void scale_kernel(int64_t n, const double *src, const double *__restrict__ d, double *dst) {
+    const double q = d[0];
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i] / q;
+}
+
+__global__ void fill_kernel(int64_t n, double *p, double v) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+unsigned elem_grid(int64_t n) { return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 4096)); }
+
+}  // namespace
+}  // namespace pjds
+
+using namespace pjds;
+
+extern "C" {
+
+int pjds_lanczos_workspace(const pjds_info *info, int64_t *vector_bytes, int64_t *scratch_bytes) {
+    if (!info || !vector_bytes || !scratch_bytes) return fail(PJDS_ERR_ARG, "NULL argument");
+    *vector_bytes = 3 * std::max<int64_t>(info->n_rows, 1) * int64_t(sizeof(double));
+    *scratch_bytes = (kRedBlocks + 8) * int64_t(sizeof(double));
+    return PJDS_OK;
+}
+
+int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                 const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
+                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, double *d_alpha,
+                 double *d_beta, void *d_vectors, void *d_scratch, void *stream) {
+    if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
+    const pjds_info &in = *info;
+    if (!(in.flags & PJDS_SYMMETRIC) || in.n_rows != in.n_cols)
+        return fail(PJDS_ERR_ARG, "Lanczos needs a square matrix converted with PJDS_SYMMETRIC");
+    if (steps < 0) return fail(PJDS_ERR_ARG, "steps %d", steps);
+    if (x_halo >= 0) {
+        if (int rc = check_xlds(in, PJDS_F64, x_halo, tile_rows)) return rc;
+    } else if (in.n_chunks && (!d_sched || !d_work)) {
+        return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
+    }
+    const int64_t n = in.n_rows;
+    if (n == 0 || steps == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_v0 || !d_alpha || !d_beta || !d_vectors || !d_scratch)
+        return fail(PJDS_ERR_ARG, "NULL device array");
+    if (in.nnz_stored && (!d_col_p || !d_val_p)) return fail(PJDS_ERR_ARG, "NULL device array");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *V = static_cast<double *>(d_vectors);
+    double *part = static_cast<double *>(d_scratch);
+    double *norm0 = part + kRedBlocks;
+    const unsigned eg = elem_grid(n);
+    // v_0 = v / ||v||, v_{-1} = 0, beta_0 = 0
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, norm0, 1);
+    hipLaunchKernelGGL(scale_kernel, dim3(eg), dim3(256), 0, s, n, d_v0, norm0, V);
+    hipLaunchKernelGGL(fill_kernel, dim3(eg), dim3(256), 0, s, n, V + 2 * n, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, int64_t(1), d_beta, 0.0);
+    for (int32_t j = 0; j < steps; ++j) {
+        double *vj = V + int64_t(j % 3) * n, *vprev = V + int64_t((j + 2) % 3) * n, *w = V + int64_t((j + 1) % 3) * n;
+        // w = A v_j - beta_j v_{j-1}
+        EpiArgs ea;
+        ea.alpha = 1.0;
+        ea.z = vprev;
+        ea.beta_dev = d_beta + j;
+        ea.bscale = -1.0;
+        if (x_halo >= 0)
+            launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, vj, w, x_halo, tile_rows, ea,
+                        PJDS_Y_PERMUTED, s);
+        else
+            launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, vj, w, ea,
+                            PJDS_Y_PERMUTED, s);
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, vj, part);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, d_alpha + j, 0);
+        hipLaunchKernelGGL(axpy_norm_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, vj, d_alpha + j, part);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, d_beta + j + 1, 1);
+        hipLaunchKernelGGL(scale_kernel, dim3(eg), dim3(256), 0, s, n, w, d_beta + j + 1, w);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PJDS_ERR_HIP, "pjds_lanczos: %s", hipGetErrorString(e));
+    return PJDS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,19 @@
+// Kernel launchers shared between the HIP translation units of libpjds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace pjds {
+// Kernel launchers shared between translation units (spmv.hip).  The caller validates.
+int check_xlds(const pjds_info &in, int32_t dtype, int32_t x_halo, int32_t tile_rows);
+void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets, const int32_t *d_col_p,
+                 const void *d_val_p, const int32_t *d_perm, int32_t dtype, const void *d_x, void *d_y,
+                 int32_t x_halo, int32_t tile_rows, const EpiArgs &ea, uint32_t flags, hipStream_t s);
+void launch_spmv_epi(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets,
+                     const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
+                     int32_t dtype, const void *d_x, void *d_y, const EpiArgs &ea, uint32_t flags,
+                     hipStream_t s);
+}  // namespace pjds
+

@@ -27,7 +27,7 @@
 #include <algorithm>
 #include <cstdint>
 
-#include "common.h"
+#include "launch.h"
 
 namespace pjds {
 namespace {
@@ -98,6 +98,23 @@ struct XStaged {
     }
 };
 
+// What a product writes: y[r] = alpha * (A x)[r] + b * z[r], with b = beta, or b = bscale *
+// (*beta_dev) when the coefficient lives in device memory (an iterative solver's scalar that
+// the host never reads).  z is indexed like y and may be y itself.  Plain product: alpha = 1,
+// z = nullptr (then y = A x exactly).
+template <class T>
+struct Epilogue {
+    T alpha, beta;
+    const T *z;
+    const T *beta_dev;
+    T bscale;
+    __device__ T operator()(T acc, int64_t r) const {
+        if (!z) return alpha * acc;
+        const T b = beta_dev ? bscale * beta_dev[0] : beta;
+        return __builtin_fma(b, z[r], alpha * acc);
+    }
+};
+
 // U consecutive entries j in [jb, jb+U) (all below the wave's longest row) added into acc:
 // U independent value/index loads, then U gathers, then U FMAs.  A lane past the end of its
 // row reads the lead row's slot (an entry that exists for every such j) and keeps acc.
@@ -159,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ sched,
     T *__restrict__ partials, int32_t *__restrict__ counters,
-    const T *__restrict__ x, T *__restrict__ y, uint32_t flags) {
+    const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
     const bool y_perm = flags & PJDS_Y_PERMUTED;
@@ -183,7 +200,10 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
             const volatile T *pp = partials + int64_t(first) * kWave + lane;
             T s = pp[0];
             for (int q = 1; q < nc; ++q) s += pp[int64_t(q) * kWave];
-            if (i < n_rows) y[y_perm ? i : perm[i]] = s;
+            if (i < n_rows) {
+                const int64_t r = y_perm ? i : perm[i];
+                y[r] = epi(s, r);
+            }
             if (lane == 0) counters[first] = 0;             // ready for the next product
         }
         return;
@@ -196,7 +216,10 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     if (split_len > 0 && m > split_len) return;            // done by the work items above
     const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : i;
     const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{x, 1, 0});
-    if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
+    if (i < n_rows) {
+        const int64_t r = y_perm ? i : perm[i];
+        y[r] = epi(acc, r);
+    }
 }
 
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_lds_kernel(
     int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
-    const int32_t *__restrict__ perm, const T *__restrict__ x, T *__restrict__ y, uint32_t flags) {
+    const int32_t *__restrict__ perm, const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
     const int lane = threadIdx.x & (kWave - 1);
@@ -234,7 +257,10 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_lds_kernel(
         const int64_t ia = i < n_pad ? i : n_pad - 1;
         const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : ia;
         const T acc = row_range_sum(ia, i_lead, len, 0, m, PjdsAddr<false, BR>{offsets}, col_p, val_p, xr);
-        if (i < n_rows) y[y_perm ? i : perm[i]] = acc;
+        if (i < n_rows) {
+            const int64_t r = y_perm ? i : perm[i];
+            y[r] = epi(acc, r);
+        }
     }
 }
 
@@ -392,6 +418,12 @@ __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__rest
     if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) out[n - 1] = in[n - 1];
 }
 
+template <class T>
+Epilogue<T> make_epi(const EpiArgs &a) {
+    return Epilogue<T>{T(a.alpha), T(a.beta), static_cast<const T *>(a.z), static_cast<const T *>(a.beta_dev),
+                       T(a.bscale)};
+}
+
 int launch_status(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(PJDS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -406,7 +438,7 @@ int64_t ws_partials_bytes(const pjds_info &in, int32_t dtype) {
 template <class T, bool JD, int BR>
 void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
                  const void *vp, const int32_t *perm, const int32_t *sched, void *work,
-                 const void *x, void *y, uint32_t flags, hipStream_t s) {
+                 const void *x, void *y, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
     const int64_t groups = ceil_div(in.n_pad, kWave);
     const int64_t waves = in.n_chunks + groups;
     const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)));
@@ -415,7 +447,7 @@ void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, con
     hipLaunchKernelGGL((pjds_spmv_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad,
                        groups, in.n_chunks, in.split_len, rl, off, cp, static_cast<const T *>(vp),
                        perm, sched, partials, counters, static_cast<const T *>(x),
-                       static_cast<T *>(y), flags);
+                       static_cast<T *>(y), make_epi<T>(ea), flags);
 }
 
 template <class T, bool JD, int BR, int LPR, int VPL>
@@ -493,6 +525,55 @@ int check_info(const pjds_info *info, int32_t dtype) {
 }
 
 }  // namespace
+
+int check_xlds(const pjds_info &in, int32_t dtype, int32_t x_halo, int32_t tile_rows) {
+    const int64_t w = in.sort_window;
+    if (!(in.flags & PJDS_LAYOUT_BLOCK) || w >= in.n_rows || w % kBlock)
+        return fail(PJDS_ERR_ARG, "x staging needs the block layout and a sort window that is a multiple of %d", kBlock);
+    if (x_halo < 0) return fail(PJDS_ERR_ARG, "x_halo %d", x_halo);
+    const int64_t tile = tile_rows == 0 ? std::max<int64_t>(w, 1024) : tile_rows;
+    if (tile < kBlock || tile % kBlock || (tile % w && w % tile))
+        return fail(PJDS_ERR_ARG, "tile_rows %lld: a multiple of %d that divides or is divided by the sort window", (long long)tile, kBlock);
+    const int64_t tsize = dtype == PJDS_F64 ? 8 : 4;
+    const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), in.n_cols);
+    if (cap * tsize > 64 * 1024) return fail(PJDS_ERR_ARG, "x range of %lld entries exceeds 64 KiB of LDS", (long long)cap);
+    return PJDS_OK;
+}
+
+void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets, const int32_t *d_col_p,
+                 const void *d_val_p, const int32_t *d_perm, int32_t dtype, const void *d_x, void *d_y,
+                 int32_t x_halo, int32_t tile_rows, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
+    const int64_t w = in.sort_window;
+    const int64_t tile = tile_rows == 0 ? std::max<int64_t>(w, 1024) : tile_rows;
+    const int64_t tsize = dtype == PJDS_F64 ? 8 : 4;
+    const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), in.n_cols);
+    const dim3 grid(unsigned(ceil_div(in.n_pad, tile)));
+    const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        const int br = in.block_height;
+#define PJDS_XLDS_CASE(B)                                                                                \
+        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B>), grid, dim3(kBlock), lds, s, in.n_rows, in.n_cols,   \
+                           in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,                  \
+                           static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
+                           static_cast<T *>(d_y), make_epi<T>(ea), flags)
+        if (br == 32) PJDS_XLDS_CASE(32);
+        else if (br == 64) PJDS_XLDS_CASE(64);
+        else PJDS_XLDS_CASE(128);
+#undef PJDS_XLDS_CASE
+    };
+    if (dtype == PJDS_F64) go(double{});
+    else go(float{});
+}
+
+void launch_spmv_epi(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets,
+                     const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
+                     int32_t dtype, const void *d_x, void *d_y, const EpiArgs &ea, uint32_t flags,
+                     hipStream_t s) {
+    dispatch<SpmvK>(dtype, !(in.flags & PJDS_LAYOUT_BLOCK), in.block_height, in, d_row_len, d_offsets, d_col_p,
+                    d_val_p, static_cast<const int32_t *>(nullptr), d_sched, d_work, d_x, d_y, ea, flags, s);
+}
+
 }  // namespace pjds
 
 using namespace pjds;
@@ -529,9 +610,29 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
     if (info->n_chunks && (!d_sched || !d_work)) return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
     dispatch<SpmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
-                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, flags,
+                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, EpiArgs{}, flags,
                     static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv");
+}
+
+int pjds_spmv_axpby(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                    const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+                    const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x,
+                    double alpha, double beta, const void *d_z, void *d_y, uint32_t flags,
+                    void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
+    if (info->n_chunks && (!d_sched || !d_work)) return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
+    if (d_z && d_z != d_y && d_z == d_x) return fail(PJDS_ERR_ARG, "z may be y but not x");
+    EpiArgs ea{alpha, beta, d_z, nullptr, 0.0};
+    dispatch<SpmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
+                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, ea, flags,
+                    static_cast<hipStream_t>(stream));
+    return launch_status("pjds_spmv_axpby");
 }
 
 int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
@@ -567,38 +668,13 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
                    void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
     if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
-    const int64_t w = info->sort_window;
-    if (!(info->flags & PJDS_LAYOUT_BLOCK) || w >= info->n_rows || w % kBlock)
-        return fail(PJDS_ERR_ARG, "x staging needs the block layout and a sort window that is a multiple of %d", kBlock);
-    if (x_halo < 0) return fail(PJDS_ERR_ARG, "x_halo %d", x_halo);
-    const int64_t tile = tile_rows == 0 ? std::max<int64_t>(w, 1024) : tile_rows;
-    if (tile < kBlock || tile % kBlock || (tile % w && w % tile))
-        return fail(PJDS_ERR_ARG, "tile_rows %lld: a multiple of %d that divides or is divided by the sort window", (long long)tile, kBlock);
-    const int64_t tsize = dtype == PJDS_F64 ? 8 : 4;
-    const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), info->n_cols);
-    if (cap * tsize > 64 * 1024) return fail(PJDS_ERR_ARG, "x range of %lld entries exceeds 64 KiB of LDS", (long long)cap);
+    if (int rc = pjds::check_xlds(*info, dtype, x_halo, tile_rows)) return rc;
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
-    const dim3 grid(unsigned(ceil_div(info->n_pad, tile)));
-    const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    auto go = [&](auto tag) {
-        using T = decltype(tag);
-        const int br = info->block_height;
-#define PJDS_XLDS_CASE(B)                                                                                \
-        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B>), grid, dim3(kBlock), lds, s, info->n_rows, info->n_cols, \
-                           info->n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,              \
-                           static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
-                           static_cast<T *>(d_y), flags)
-        if (br == 32) PJDS_XLDS_CASE(32);
-        else if (br == 64) PJDS_XLDS_CASE(64);
-        else PJDS_XLDS_CASE(128);
-#undef PJDS_XLDS_CASE
-    };
-    if (dtype == PJDS_F64) go(double{});
-    else go(float{});
+    pjds::launch_xlds(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, dtype, d_x, d_y, x_halo, tile_rows,
+                      EpiArgs{}, flags, static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv_xlds");
 }
 

@@ -91,6 +91,38 @@ class PjdsMatrix:
                     d["sched"] if self.info.n_chunks else None, d["work"], x, y, flags, stream)
         return y
 
+    def spmv_axpby(self, x: torch.Tensor, y: torch.Tensor, alpha: float = 1.0, beta: float = 0.0,
+                   z: torch.Tensor | None = None, y_permuted: bool = False, stream=None) -> torch.Tensor:
+        """y = alpha (A x) + beta z (z may be y: accumulate)."""
+        flags = L.PJDS_Y_PERMUTED if y_permuted else 0
+        d = self.d
+        L.pjds_spmv_axpby(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"],
+                          d["sched"] if self.info.n_chunks else None, d["work"], x, alpha, beta, z, y,
+                          flags, stream)
+        return y
+
+    def lanczos_buffers(self) -> dict:
+        """Device buffers for lanczos(): reuse them across calls (and inside a captured graph)."""
+        vb, sb = L.pjds_lanczos_workspace(self.info)
+        return {"vectors": torch.empty(vb // 8, dtype=torch.float64, device=self.device),
+                "scratch": torch.empty(sb // 8, dtype=torch.float64, device=self.device)}
+
+    def lanczos(self, v0: torch.Tensor, steps: int, x_halo: int = -1, tile_rows: int = 0,
+                alpha: torch.Tensor | None = None, beta: torch.Tensor | None = None,
+                buffers: dict | None = None, stream=None):
+        """Lanczos coefficients (alpha [steps], beta [steps+1]) from start vector v0, given in the
+        permuted basis; the matrix must have been converted with symmetric=True."""
+        if alpha is None:
+            alpha = torch.empty(max(steps, 1), dtype=torch.float64, device=self.device)
+        if beta is None:
+            beta = torch.empty(steps + 1, dtype=torch.float64, device=self.device)
+        b = buffers or self.lanczos_buffers()
+        d = self.d
+        L.pjds_lanczos(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"],
+                       d["sched"] if self.info.n_chunks else None, d["work"], v0, steps, x_halo, tile_rows,
+                       alpha, beta, b["vectors"], b["scratch"], stream)
+        return alpha[:steps], beta
+
     def spmv_xlds(self, x: torch.Tensor, y: torch.Tensor | None = None, x_halo: int = 512,
                   tile_rows: int = 0, y_permuted: bool = False, xcd_remap: bool = False,
                   stream=None) -> torch.Tensor:
@@ -220,3 +252,25 @@ class PjdsBatch:
             self.close()
         except Exception:
             pass
+
+
+def split_columns(A, c0: int, c1: int):
+    """A = A_local + A_nonlocal with A_local holding the entries whose column lies in [c0, c1)
+    (the local/non-local split of a row-distributed product); both keep A's row count and the
+    entries' order.  Returns two objects with n_rows, n_cols, row_ptr, col, val."""
+    class _Part:
+        pass
+    rp = np.asarray(A.row_ptr, np.int64)
+    col = np.asarray(A.col)
+    val = np.asarray(A.val)
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(rp))
+    out = []
+    for keep in ((col >= c0) & (col < c1), ~((col >= c0) & (col < c1))):
+        P = _Part()
+        P.n_rows, P.n_cols = A.n_rows, A.n_cols
+        counts = np.bincount(rows[keep], minlength=A.n_rows)
+        P.row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        P.col = np.ascontiguousarray(col[keep], dtype=np.int32)
+        P.val = np.ascontiguousarray(val[keep])
+        out.append(P)
+    return out[0], out[1]

@@ -60,10 +60,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_pjds_sort.restype = ctypes.c_int64
         L.oracle_pjds_block_max.argtypes = [ctypes.c_int64, ctypes.c_int64, _i32p, _i64p]
         L.oracle_pjds_col_start.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _i64p]
-        L.oracle_pjds_block_start.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i64p]
-        L.oracle_pjds_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+        L.oracle_pjds_block_start.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p, _i64p]
+        L.oracle_pjds_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                        _i64p, _i32p, _f64p, _i32p, _i64p, ctypes.c_int64, _i32p, _f64p]
-        L.oracle_pjds_spmv.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i32p, _i64p,
+        L.oracle_pjds_spmv.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i32p, _i64p,
                                        _i32p, _f64p, _f64p, _f64p]
         L.oracle_ellr_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p, _i32p,
                                        _f64p, _i32p, _i32p, _f64p]
@@ -105,11 +105,12 @@ def csr_spmmv(A, X: np.ndarray) -> np.ndarray:
 
 
 def pjds_build(A, b_r: int = 64, window: int | None = None, layout: str = "jd",
-               symmetric: bool = False) -> dict:
+               symmetric: bool = False, lanes: int = 1) -> dict:
     """The pJDS arrays of A (see ``oracle.c`` for the construction and its citations).
 
     ``window`` None or >= n_rows is a global sort.  ``layout`` "jd" (Listing 2, requires a
-    global sort) or "block".  Returns perm, row_len, block_max, offsets, col_p, val_p and
+    global sort) or "block"; ``lanes`` > 1 (block layout only) stores T = lanes consecutive
+    slots per row and step.  Returns perm, row_len, block_max, offsets, col_p, val_p and
     the sizes n_pad, n_blocks, nnz_stored, max_row_len.
     """
     n = A.n_rows
@@ -118,6 +119,8 @@ def pjds_build(A, b_r: int = 64, window: int | None = None, layout: str = "jd",
     lay = {"jd": 0, "block": 1}[layout]
     if lay == 0 and w != 0:
         raise ValueError("JD layout needs a global sort")
+    if lanes < 1 or (lanes > 1 and lay == 0):
+        raise ValueError("lanes per row >= 1, and > 1 only with the block layout")
     if symmetric and A.n_rows != A.n_cols:
         raise ValueError("symmetric renumbering needs a square matrix")
     n_pad_guess = (n + b_r - 1) // b_r * b_r
@@ -139,14 +142,14 @@ def pjds_build(A, b_r: int = 64, window: int | None = None, layout: str = "jd",
     else:
         offsets = np.zeros(n_blocks + 1, dtype=np.int64)
         bm = _c(block_max, np.int64) if n_blocks else np.zeros(1, np.int64)
-        lib().oracle_pjds_block_start(n_blocks, b_r, _p(bm, _i64p), _p(offsets, _i64p))
+        lib().oracle_pjds_block_start(n_blocks, b_r, lanes, _p(bm, _i64p), _p(offsets, _i64p))
     nnz_stored = int(offsets[-1])
     col_p = np.zeros(max(nnz_stored, 1), dtype=np.int32)
     val_p = np.zeros(max(nnz_stored, 1), dtype=np.float64)
     col = _c(A.col, np.int32) if A.nnz else np.zeros(1, np.int32)
     val = _c(A.val, np.float64) if A.nnz else np.zeros(1, np.float64)
     perm_c = perm if n else np.zeros(1, np.int32)
-    lib().oracle_pjds_fill(n, b_r, lay, int(bool(symmetric)), _p(rp, _i64p), _p(col, _i32p),
+    lib().oracle_pjds_fill(n, b_r, lanes, lay, int(bool(symmetric)), _p(rp, _i64p), _p(col, _i32p),
                            _p(val, _f64p), _p(perm_c, _i32p), _p(offsets, _i64p), nnz_stored,
                            _p(col_p, _i32p), _p(val_p, _f64p))
     col_p, val_p = col_p[:nnz_stored], val_p[:nnz_stored]
@@ -154,7 +157,8 @@ def pjds_build(A, b_r: int = 64, window: int | None = None, layout: str = "jd",
         val_p = val_p.astype(np.float32)          # exact: every value came from float32
     return dict(perm=perm, row_len=row_len, block_max=block_max, offsets=offsets, col_p=col_p,
                 val_p=val_p, n_pad=int(n_pad), n_blocks=int(n_blocks), nnz_stored=nnz_stored,
-                max_row_len=max_len, b_r=b_r, layout=layout, n_rows=n, symmetric=bool(symmetric))
+                max_row_len=max_len, b_r=b_r, layout=layout, n_rows=n, symmetric=bool(symmetric),
+                lanes=lanes)
 
 
 def pjds_spmv(P: dict, x: np.ndarray) -> np.ndarray:
@@ -165,7 +169,7 @@ def pjds_spmv(P: dict, x: np.ndarray) -> np.ndarray:
     y = np.empty(max(n, 1), dtype=np.float64)
     col_p = P["col_p"] if P["nnz_stored"] else np.zeros(1, np.int32)
     val_p = _c(P["val_p"], np.float64) if P["nnz_stored"] else np.zeros(1)
-    lib().oracle_pjds_spmv(n, P["b_r"], {"jd": 0, "block": 1}[P["layout"]],
+    lib().oracle_pjds_spmv(n, P["b_r"], P.get("lanes", 1), {"jd": 0, "block": 1}[P["layout"]],
                            _p(_c(P["row_len"], np.int32), _i32p), _p(_c(P["offsets"], np.int64), _i64p),
                            _p(_c(col_p, np.int32), _i32p), _p(val_p, _f64p), _p(x, _f64p), _p(y, _f64p))
     return y[:n]

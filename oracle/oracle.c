@@ -79,7 +79,12 @@ void oracle_csr_spmmv(int64_t n_rows, const int64_t *row_ptr, const int32_t *col
  *                           whose longest row exceeds j (needs a global sort, so that those
  *                           blocks come first);
  *   block layout:           block_start[b] + j*b_r + (i mod b_r), b = i / b_r, each block
- *                           stored as its own b_r x M_b column-major tile.
+ *                           stored as its own b_r x M_b column-major tile;
+ *   block layout, T lanes:  T consecutive slots per row and step, the sliced ELLR-T idea
+ *                           that the outlook (Sect. 4) names: entry j of sorted row i sits in
+ *                           step s = j / T of its block, at block_start[b] + s*(b_r*T)
+ *                           + (i mod b_r)*T + (j mod T).  A block holds ceil(M_b / T) steps.
+ *                           T = 1 is the block layout above.
  * Padding slots hold value 0 and column 0.  The result row i of the permuted product is
  * original row perm[i].
  */
@@ -149,19 +154,30 @@ void oracle_pjds_col_start(int64_t n_blocks, int64_t b_r, const int64_t *block_m
     }
 }
 
-/* Block layout offsets: block_start[b+1] = block_start[b] + b_r * block_max[b]. */
-void oracle_pjds_block_start(int64_t n_blocks, int64_t b_r, const int64_t *block_max,
+/* Block layout offsets with T lanes per row: block_start[b+1] = block_start[b] +
+ * b_r * T * ceil(block_max[b] / T)  (T = 1: b_r * block_max[b]). */
+void oracle_pjds_block_start(int64_t n_blocks, int64_t b_r, int64_t lanes, const int64_t *block_max,
                              int64_t *block_start)
 {
     block_start[0] = 0;
-    for (int64_t b = 0; b < n_blocks; ++b)
-        block_start[b + 1] = block_start[b] + b_r * block_max[b];
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        int64_t steps = (block_max[b] + lanes - 1) / lanes;
+        block_start[b + 1] = block_start[b] + b_r * lanes * steps;
+    }
+}
+
+/* Where entry j of sorted row i is stored (layout 0 = JD, 1 = block with `lanes` lanes). */
+static int64_t oracle_slot(int32_t layout, int64_t b_r, int64_t lanes, const int64_t *offsets,
+                           int64_t i, int64_t j)
+{
+    if (layout == 0) return offsets[j] + i;
+    return offsets[i / b_r] + (j / lanes) * (b_r * lanes) + (i % b_r) * lanes + j % lanes;
 }
 
 /* Fill the stored arrays (nnz_stored entries each).  layout 0 = JD (offsets = col_start),
- * 1 = block (offsets = block_start).  symmetric != 0 renumbers columns into the permuted
- * basis: col_p = invperm[col] (square matrices only). */
-void oracle_pjds_fill(int64_t n_rows, int64_t b_r, int32_t layout, int32_t symmetric,
+ * 1 = block (offsets = block_start) with `lanes` lanes per row.  symmetric != 0 renumbers
+ * columns into the permuted basis: col_p = invperm[col] (square matrices only). */
+void oracle_pjds_fill(int64_t n_rows, int64_t b_r, int64_t lanes, int32_t layout, int32_t symmetric,
                       const int64_t *row_ptr, const int32_t *col, const double *val,
                       const int32_t *perm, const int64_t *offsets, int64_t nnz_stored,
                       int32_t *col_p, double *val_p)
@@ -176,8 +192,7 @@ void oracle_pjds_fill(int64_t n_rows, int64_t b_r, int32_t layout, int32_t symme
         int64_t src = perm[i];
         int64_t len = row_ptr[src + 1] - row_ptr[src];
         for (int64_t j = 0; j < len; ++j) {
-            int64_t a = layout == 0 ? offsets[j] + i
-                                    : offsets[i / b_r] + j * b_r + (i % b_r);
+            int64_t a = oracle_slot(layout, b_r, lanes, offsets, i, j);
             int32_t c = col[row_ptr[src] + j];
             col_p[a] = symmetric ? invperm[c] : c;
             val_p[a] = val[row_ptr[src] + j];
@@ -189,15 +204,14 @@ void oracle_pjds_fill(int64_t n_rows, int64_t b_r, int32_t layout, int32_t symme
 /* y_p = (pJDS matrix) x with the oracle's own arrays, Listing 2 read literally: for sorted
  * row i, sum over j < row_len[i] of val_p * x[col_p] in j order.  Used only to tie the
  * oracle's construction to the plain product. */
-void oracle_pjds_spmv(int64_t n_rows, int64_t b_r, int32_t layout, const int32_t *row_len,
+void oracle_pjds_spmv(int64_t n_rows, int64_t b_r, int64_t lanes, int32_t layout, const int32_t *row_len,
                       const int64_t *offsets, const int32_t *col_p, const double *val_p,
                       const double *x, double *y_perm)
 {
     for (int64_t i = 0; i < n_rows; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < row_len[i]; ++j) {
-            int64_t a = layout == 0 ? offsets[j] + i
-                                    : offsets[i / b_r] + j * b_r + (i % b_r);
+            int64_t a = oracle_slot(layout, b_r, lanes, offsets, i, j);
             double p = val_p[a] * x[col_p[a]];
             s = s + p;
         }

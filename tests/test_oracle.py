@@ -100,16 +100,23 @@ def test_spmmv_equals_dense_bruteforce(k):
 
 # ---------------------------------------------------------------- pJDS construction
 
+def slot(P, i, j):
+    """Stored position of entry j of sorted row i: Listing 2's col_start[j] + i, the block
+    tile's block_start[b] + j b_r + r, or with T lanes per row step j // T of the block, lane
+    slot r T + j % T."""
+    if P["layout"] == "jd":
+        return P["offsets"][j] + i
+    b_r, T = P["b_r"], P.get("lanes", 1)
+    return P["offsets"][i // b_r] + (j // T) * (b_r * T) + (i % b_r) * T + j % T
+
+
 def decode_pjds(P, A):
-    """Read the stored arrays back through the addressing rule (Listing 2 / block tiles)."""
+    """Read the stored arrays back through the addressing rule."""
     rows = []
     for i in range(P["n_rows"]):
         ent = []
         for j in range(P["row_len"][i]):
-            if P["layout"] == "jd":
-                a = P["offsets"][j] + i
-            else:
-                a = P["offsets"][i // P["b_r"]] + j * P["b_r"] + i % P["b_r"]
+            a = slot(P, i, j)
             ent.append((int(P["col_p"][a]), float(P["val_p"][a])))
         rows.append(ent)
     return rows
@@ -135,8 +142,9 @@ def check_invariants(A, P, window):
     for i in range(n - 1):
         if P["row_len"][i] == P["row_len"][i + 1] and (i // w) == ((i + 1) // w):
             assert perm[i] < perm[i + 1]
-    # stored count = b_r * sum of block maxima
-    assert P["nnz_stored"] == b_r * int(P["block_max"].sum())
+    # stored count = b_r * sum of block maxima (T lanes: b_r T * sum of ceil(M_b / T))
+    T = P.get("lanes", 1)
+    assert P["nnz_stored"] == b_r * T * int(((P["block_max"] + T - 1) // T).sum())
     # round trip: entries and their order reproduce the input exactly
     rows = decode_pjds(P, A)
     for i in range(n):
@@ -147,7 +155,7 @@ def check_invariants(A, P, window):
     used = np.zeros(P["nnz_stored"], bool)
     for i in range(P["n_pad"]):
         for j in range(P["row_len"][i]):
-            a = (P["offsets"][j] + i) if P["layout"] == "jd" else P["offsets"][i // b_r] + j * b_r + i % b_r
+            a = slot(P, i, j)
             assert not used[a]
             used[a] = True
     assert np.all(P["val_p"][~used] == 0) and np.all(P["col_p"][~used] == 0)
@@ -185,6 +193,60 @@ def test_pjds_product_equals_plain_product(seed, layout, window):
     x = synth.dense_x(190, seed)
     P = oracle.pjds_build(A, b_r=32, window=window, layout=layout)
     assert np.array_equal(oracle.pjds_spmv(P, x), oracle.csr_spmv(A, x)[P["perm"]])
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("b_r,lanes,window", [(32, 2, None), (16, 4, 64), (8, 8, 128), (1, 64, None), (3, 5, 9)])
+def test_pjds_lanes_invariants_and_product(seed, b_r, lanes, window):
+    # T lanes per row (the sliced ELLR-T idea of the outlook, Sect. 4): same sort, same rows,
+    # each block stored as ceil(M_b / T) steps of b_r T slots; the product in stored order is
+    # still CSR order, so it is bit-identical to the plain one
+    A = synth.random_csr(311, 150, seed + 40, max_len=70)
+    P = oracle.pjds_build(A, b_r=b_r, window=window, layout="block", lanes=lanes)
+    check_invariants(A, P, window)
+    x = synth.dense_x(150, seed)
+    assert np.array_equal(oracle.pjds_spmv(P, x), oracle.csr_spmv(A, x)[P["perm"]])
+
+
+def test_pjds_one_lane_is_the_block_layout():
+    A = synth.random_csr(500, 300, 9, max_len=25)
+    P1 = oracle.pjds_build(A, b_r=64, window=128, layout="block", lanes=1)
+    P0 = oracle.pjds_build(A, b_r=64, window=128, layout="block")
+    for k in ("perm", "row_len", "offsets", "col_p", "val_p"):
+        assert np.array_equal(P1[k], P0[k]), k
+
+
+def test_pjds_lanes_single_row_is_the_row_itself():
+    # one row of length 100, b_r = 1 and T = 64: the row is stored contiguously in its own
+    # order, padded to the next multiple of 64 (two steps of 64 slots)
+    row = synth.CSR(1, 500, np.array([0, 100], np.int64), np.arange(0, 500, 5, dtype=np.int32),
+                    np.arange(1, 101, dtype=np.float64))
+    P = oracle.pjds_build(row, b_r=1, layout="block", lanes=64)
+    assert P["nnz_stored"] == 128 and list(P["offsets"]) == [0, 128]
+    assert np.array_equal(P["val_p"][:100], row.val) and np.array_equal(P["col_p"][:100], row.col)
+    assert np.all(P["val_p"][100:] == 0) and np.all(P["col_p"][100:] == 0)
+
+
+def test_pjds_lanes_hand_worked_block():
+    # rows of lengths 3 and 2 (values 1 2 3 | 4 5), one block of b_r = 2 rows, T = 2 lanes:
+    # step 0 holds row 0's entries 0, 1 then row 1's entries 0, 1; step 1 holds row 0's
+    # entry 2, then padding
+    A = synth.CSR(2, 4, np.array([0, 3, 5], np.int64), np.array([0, 1, 3, 1, 2], np.int32),
+                  np.array([1.0, 2.0, 3.0, 4.0, 5.0]))
+    P = oracle.pjds_build(A, b_r=2, layout="block", lanes=2)
+    assert list(P["offsets"]) == [0, 8]
+    assert list(P["val_p"]) == [1.0, 2.0, 4.0, 5.0, 3.0, 0.0, 0.0, 0.0]
+    assert list(P["col_p"]) == [0, 1, 1, 2, 3, 0, 0, 0]
+
+
+@pytest.mark.parametrize("L,T", [(8, 2), (8, 4), (12, 4), (16, 16)])
+def test_pjds_lanes_constant_length_no_overhead(L, T):
+    # every row of length L with T dividing L: no padding at all, nnz_stored = N_pad L
+    n = 64 * 5
+    A = synth.CSR(n, n, np.arange(0, n * L + 1, L, dtype=np.int64),
+                  (np.arange(n * L, dtype=np.int64) % n).astype(np.int32), np.ones(n * L))
+    P = oracle.pjds_build(A, b_r=64 // T, layout="block", lanes=T)
+    assert P["nnz_stored"] == n * L
 
 
 def test_pjds_symmetric_renumbering():

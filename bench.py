@@ -160,6 +160,8 @@ def main() -> int:
     ap.add_argument("--x-halo", type=int, default=512,
                     help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0); -1: x through the caches")
     ap.add_argument("--tile-rows", type=int, default=512, help="rows per workgroup of the LDS path")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="lanes per row (power of two up to 64, block layout, x through the caches)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip comparison legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-matrix batch leg")
@@ -176,6 +178,9 @@ def main() -> int:
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    if args.lanes > 1 and (args.x_halo >= 0 or args.layout != "block"):
+        print(json.dumps({"error": "--lanes > 1 needs --layout block and --x-halo -1"}))
         return 2
     _lib.lib()   # fail loudly if the HIP library is not built
 
@@ -194,7 +199,7 @@ def main() -> int:
     t0 = time.perf_counter()
     M = PjdsMatrix.from_csr(A, block_height=args.block_height, layout=args.layout,
                             sort_window=args.sort_window, symmetric=args.mode == "symmetric",
-                            split_len=args.split_len, keep_host=args.mode == "symmetric")
+                            split_len=args.split_len, keep_host=args.mode == "symmetric", lanes=args.lanes)
     t_conv = time.perf_counter() - t0
     perm = M.d["perm"]
     x_dev = torch.from_numpy(x_np).to("cuda", tdt)
@@ -236,7 +241,8 @@ def main() -> int:
         import oracle
         out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
 
-    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_t{args.tile_rows}_{args.mode}")
+    lanes_key = f"_T{args.lanes}" if args.lanes > 1 else ""
+    traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_t{args.tile_rows}_{args.mode}{lanes_key}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",
         "value": round(gbs, 2),
@@ -250,14 +256,16 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic (seeded generator standing in for the paper's Holstein-Hubbard matrix)",
-        "config": {"workload": desc, "n_rows": n, "nnz": nnz, "block_height": args.block_height,
+        "config": {"workload": desc, "n_rows": n, "nnz": nnz, "block_height": M.info.block_height,
+                   "lanes_per_row": args.lanes,
                    "layout": args.layout, "mode": args.mode, "nnz_stored": M.info.nnz_stored,
                    "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
                    "tile_rows": args.tile_rows if args.x_halo >= 0 else None,
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "pjds_spmv_lds_kernel" if args.x_halo >= 0 else "pjds_spmv_kernel",
+                     "kernel": "pjds_spmv_lds_kernel" if args.x_halo >= 0 else
+                               ("pjds_lanes_kernel" if args.lanes > 1 else "pjds_spmv_kernel"),
                      "alg_bytes_per_launch": b_alg},
         "cpu_baseline": cpu,
         "gflops": round(gflops, 2),
@@ -283,6 +291,22 @@ def main() -> int:
 
     if not args.no_extra:
         extra = {}
+        # cold Infinity Cache: the median of single products, each after a 1 GiB streaming
+        # pass over another buffer evicts the matrix from the 256 MB MALL
+        flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        flush.fill_(1.0)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(21)]
+        for s0, s1 in ev:
+            flush.mul_(1.0)
+            s0.record()
+            step()
+            s1.record()
+        torch.cuda.synchronize()
+        cold = sorted(s0.elapsed_time(s1) for s0, s1 in ev[1:])
+        ms_cold = cold[len(cold) // 2]
+        extra["cold_mall"] = {"reps": len(cold), "median_ms": round(ms_cold, 5),
+                              "GBps_alg": round(b_alg / ms_cold / 1e6, 1)}
+        del flush
         # same matrix in the comparison formats
         log("ELLPACK-R and CSR legs")
         info_e = EllrMatrix.plan(A)
@@ -383,17 +407,37 @@ def main() -> int:
             yh.copy_(y_dev, non_blocking=True)
         ms_link = time_launches(with_link, 20, 3)
         from paper_1112_5588_amd import model as pmodel
-        b_pci = 2 * vbytes * n / ((ms_h2d + ms_d2h) * 1e-3)
+        # eq. (2): B_GPU is the device's streaming bandwidth (the read probe), B_PCI the measured
+        # round trip of x and y over the host link; alpha at its minimum 1/N_nzr
         nnzr = nnz / n
+        b_gpu = result["hbm_probe"]["read_GBps"] * 1e9
+        b_pci = 2 * vbytes * n / ((ms_h2d + ms_d2h) * 1e-3)
+        ratio = b_gpu / b_pci
+        t_mvm_model = pmodel.t_mvm(n, nnzr, 1.0 / nnzr, b_gpu)
+        t_pci_model = pmodel.t_pci(n, b_pci)
         extra["host_link"] = {
             "h2d_GBps": round(vbytes * n / ms_h2d / 1e6, 1), "d2h_GBps": round(vbytes * n / ms_d2h / 1e6, 1),
-            "ms_product": round(ms, 5), "ms_with_transfers": round(ms_link, 5),
-            "transfer_share": round(1 - ms / ms_link, 4),
-            "bw_ratio_gpu_over_link": round(gbs * 1e9 / b_pci, 2),
-            "eq3_nnzr_bound_half_penalty_alpha1": round(pmodel.nnzr_bound_half_penalty(gbs * 1e9 / b_pci, 1.0), 1),
-            "eq4_nnzr_bound_tenth_penalty_alpha1": round(pmodel.nnzr_bound_tenth_penalty(gbs * 1e9 / b_pci, 1.0), 1),
-            "n_nzr": round(nnzr, 2)}
+            "B_gpu_over_B_pci": round(ratio, 2), "n_nzr": round(nnzr, 2),
+            "ms_product": round(ms, 5), "ms_product_eq2": round(t_mvm_model * 1e3, 5),
+            "ms_transfers_eq2": round(t_pci_model * 1e3, 5), "ms_with_transfers": round(ms_link, 5),
+            "transfer_share_measured": round(1 - ms / ms_link, 4),
+            "transfer_share_eq2": round(t_pci_model / (t_pci_model + t_mvm_model), 4),
+            "eq3_nnzr_max_half_penalty": {"alpha0": round(pmodel.nnzr_bound_half_penalty(ratio, 0.0), 1),
+                                          "alpha1": round(pmodel.nnzr_bound_half_penalty(ratio, 1.0), 1)},
+            "eq4_nnzr_min_tenth_penalty": {"alpha0": round(pmodel.nnzr_bound_tenth_penalty(ratio, 0.0), 1),
+                                           "alpha1": round(pmodel.nnzr_bound_tenth_penalty(ratio, 1.0), 1)}}
         del xh, yh, xd2
+        # T lanes per row (block layout, same sort window, x through the caches) on this matrix
+        lanes_leg = {}
+        for T in (2, 4, 8):
+            Ml = PjdsMatrix.from_csr(A, layout="block", sort_window=args.sort_window, lanes=T)
+            xo = torch.from_numpy(x_np).to("cuda", tdt)
+            yl = torch.empty(n, dtype=tdt, device="cuda")
+            ms_t = time_launches(lambda: Ml.spmv(xo, yl, y_permuted=True), 50, 5)
+            lanes_leg[f"T{T}"] = {"ms": round(ms_t, 5), "GBps_alg": round(b_alg / ms_t / 1e6, 1),
+                                  "nnz_stored": Ml.info.nnz_stored}
+            del Ml
+        extra["lanes_per_row"] = lanes_leg
         # local/non-local split (vector mode with overlap): y written, then read and written again
         from paper_1112_5588_amd.matrix import split_columns
         loc, nl = split_columns(A, 0, A.n_cols // 2)

@@ -60,6 +60,19 @@ extern "C" {
                                     coalesced; default scatters y to the original row order       */
 #define PJDS_XCD_REMAP     0x8u  /* renumber workgroups so each of the 8 XCDs processes one
                                     contiguous range of row blocks (default: hardware round robin) */
+/* Lanes per row (conversion flag, with PJDS_LAYOUT_BLOCK): PJDS_LANES(k) lets T = 2^k lanes
+ * (k = 1..6) share each sorted row, the idea of the sliced ELLR-T format that the outlook of
+ * Sect. 4 names beside pJDS.  The block height must then be b_r = 64 / T, so one block fills
+ * one 64-lane wavefront.  A block of longest row M_b stores W_b = ceil(M_b / T) steps of 64
+ * slots; entry j of sorted row i sits at
+ *     block_start[i / b_r] + (j / T) * 64 + (i mod b_r) * T + (j mod T),
+ * so lane t of a row takes entries t, t + T, t + 2T, ... and every step of the wave is one
+ * contiguous 64-slot segment.  nnz_stored = 64 * sum_b W_b.  PJDS_LANES(0) is the plain
+ * block layout.  Long-row splitting does not apply (n_chunks = 0); pjds_spmv and
+ * pjds_spmv_axpby accept such matrices, the other products return PJDS_ERR_UNSUPPORTED. */
+#define PJDS_LANES_SHIFT   8
+#define PJDS_LANES_MASK    (0x7u << PJDS_LANES_SHIFT)
+#define PJDS_LANES(k)      ((uint32_t)(k) << PJDS_LANES_SHIFT)
 
 /* ---- pJDS -------------------------------------------------------------------------- */
 /*
@@ -92,7 +105,7 @@ typedef struct pjds_info {
     int64_t  n_offsets;      /* entries of the offsets array                               */
     int32_t  block_height;   /* b_r: 32, 64 or 128                                         */
     int32_t  max_row_len;    /* longest row                                                */
-    uint32_t flags;          /* PJDS_LAYOUT_* | PJDS_SYMMETRIC, as planned                 */
+    uint32_t flags;          /* PJDS_LAYOUT_* | PJDS_SYMMETRIC | PJDS_LANES(k), as planned  */
     int32_t  split_len;      /* long-row threshold and work-item length; 0 = never split  */
     int64_t  n_chunks;       /* work items of split wave groups (0 if none)               */
     int64_t  n_split_groups; /* wave groups that are split                                 */
@@ -100,10 +113,11 @@ typedef struct pjds_info {
 
 /*
  * Validate row_ptr (host, n_rows + 1 entries, row_ptr[0] = 0, non-decreasing) and size the
- * pJDS format.  block_height must be 32, 64 or 128 (the MI355X wavefront is 64 lanes).
- * sort_window <= 0 or >= n_rows means a global sort; otherwise it must be a positive
- * multiple of 64 and of block_height.  flags: PJDS_LAYOUT_* | PJDS_SYMMETRIC; the JD layout
- * needs a global sort.  split_len < 0 disables long-row splitting, 0 picks the default
+ * pJDS format.  block_height must be 32, 64 or 128 (the MI355X wavefront is 64 lanes), or
+ * 64 / T with PJDS_LANES(k), T = 2^k.  sort_window <= 0 or >= n_rows means a global sort;
+ * otherwise it must be a positive multiple of 64 and of block_height.  flags:
+ * PJDS_LAYOUT_* | PJDS_SYMMETRIC | PJDS_LANES(k); the JD layout needs a global sort, and
+ * PJDS_LANES(k > 0) needs the block layout.  split_len < 0 disables long-row splitting, 0 picks the default
  * (128), > 0 sets it (a multiple of 8).
  * Errors: ERR_ARG, ERR_INDEX, ERR_OVERFLOW (nnz_stored or n_pad >= 2^31 rows).
  */

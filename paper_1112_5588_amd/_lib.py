@@ -31,6 +31,13 @@ PJDS_LAYOUT_BLOCK = 0x1
 PJDS_SYMMETRIC = 0x2
 PJDS_Y_PERMUTED = 0x4
 PJDS_XCD_REMAP = 0x8
+PJDS_LANES_SHIFT = 8
+PJDS_LANES_MASK = 0x7 << PJDS_LANES_SHIFT
+
+
+def PJDS_LANES(k: int) -> int:
+    """Conversion flag for T = 2^k lanes per sorted row (block layout, block height 64 / T)."""
+    return (int(k) << PJDS_LANES_SHIFT) & PJDS_LANES_MASK
 
 
 class PjdsError(RuntimeError):

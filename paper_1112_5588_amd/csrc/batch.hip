@@ -222,6 +222,10 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
         const pjds_info &in = *m.info;
         if (in.block_height != first.block_height || (in.flags & PJDS_LAYOUT_BLOCK) != (first.flags & PJDS_LAYOUT_BLOCK))
             return fail(PJDS_ERR_ARG, "member %d: every member needs the same block height and layout", k);
+        if (in.flags & PJDS_LANES_MASK)
+            return fail(PJDS_ERR_UNSUPPORTED, "member %d: a matrix with several lanes per row cannot join a batch", k);
+        if (in.block_height != 32 && in.block_height != 64 && in.block_height != 128)
+            return fail(PJDS_ERR_ARG, "member %d: block_height %d", k, in.block_height);
         if (in.n_rows < 0 || in.n_pad < in.n_rows || in.n_pad % in.block_height)
             return fail(PJDS_ERR_ARG, "member %d: inconsistent info", k);
         if (in.n_rows && (!m.d_row_len || !m.d_offsets || !m.d_y))

@@ -122,13 +122,18 @@ void sort_rows(int64_t n_rows, int64_t n_pad, int64_t window, const int64_t *row
     for (int64_t i = n_rows; i < n_pad; ++i) row_len[i] = 0;
 }
 
+// T = 2^k lanes per row from the conversion flags (1 without PJDS_LANES).
+inline int32_t lanes_per_row(uint32_t flags) { return int32_t(1) << ((flags & PJDS_LANES_MASK) >> PJDS_LANES_SHIFT); }
+
 struct Plan {
     int64_t n_pad = 0, n_blocks = 0, nnz_stored = 0, n_chunks = 0, n_split = 0;
     int32_t max_len = 0;
     std::vector<int64_t> block_max;
 };
 
-void size_blocks(int64_t n_pad, int32_t b_r, int32_t split_len, const int32_t *row_len, Plan &p) {
+// Block maxima, stored entries (b_r * T * ceil(M_b / T) per block) and the long-row work
+// items of wave groups longer than split_len.
+void size_blocks(int64_t n_pad, int32_t b_r, int32_t lanes, int32_t split_len, const int32_t *row_len, Plan &p) {
     p.n_pad = n_pad;
     p.n_blocks = n_pad / b_r;
     p.block_max.assign(size_t(p.n_blocks), 0);
@@ -138,7 +143,7 @@ void size_blocks(int64_t n_pad, int32_t b_r, int32_t split_len, const int32_t *r
         int32_t m = 0;
         for (int32_t r = 0; r < b_r; ++r) m = std::max(m, row_len[b * b_r + r]);
         p.block_max[size_t(b)] = m;
-        stored += int64_t(b_r) * m;
+        stored += int64_t(b_r) * lanes * ceil_div(m, lanes);
         mx = std::max(mx, m);
     }
     p.nnz_stored = stored;
@@ -161,10 +166,17 @@ int plan_common(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, int32_t 
                 int64_t sort_window, uint32_t flags, int32_t split_len, int64_t &window,
                 int32_t &split) {
     if (int rc = check_row_ptr(n_rows, n_cols, row_ptr)) return rc;
-    if (b_r != 32 && b_r != 64 && b_r != 128)
-        return fail(PJDS_ERR_ARG, "block_height %d: must be 32, 64 or 128", b_r);
-    if (flags & ~(PJDS_LAYOUT_BLOCK | PJDS_SYMMETRIC))
+    if (flags & ~(PJDS_LAYOUT_BLOCK | PJDS_SYMMETRIC | PJDS_LANES_MASK))
         return fail(PJDS_ERR_ARG, "unknown conversion flags 0x%x", flags);
+    const int32_t lanes = lanes_per_row(flags);
+    if (lanes > kWave) return fail(PJDS_ERR_ARG, "PJDS_LANES(k) needs k <= 6");
+    if (lanes > 1) {
+        if (!(flags & PJDS_LAYOUT_BLOCK)) return fail(PJDS_ERR_ARG, "PJDS_LANES needs PJDS_LAYOUT_BLOCK");
+        if (b_r != kWave / lanes)
+            return fail(PJDS_ERR_ARG, "block_height %d: with %d lanes per row it must be %d", b_r, lanes, kWave / lanes);
+    } else if (b_r != 32 && b_r != 64 && b_r != 128) {
+        return fail(PJDS_ERR_ARG, "block_height %d: must be 32, 64 or 128", b_r);
+    }
     if ((flags & PJDS_SYMMETRIC) && n_rows != n_cols)
         return fail(PJDS_ERR_ARG, "PJDS_SYMMETRIC needs a square matrix (%lld x %lld)", (long long)n_rows, (long long)n_cols);
     if (sort_window <= 0 || sort_window >= n_rows) {
@@ -177,7 +189,7 @@ int plan_common(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, int32_t 
             return fail(PJDS_ERR_ARG, "the JD layout needs a global sort; use PJDS_LAYOUT_BLOCK with a sort window");
         window = sort_window;
     }
-    if (split_len < 0) split = 0;
+    if (split_len < 0 || lanes > 1) split = 0;
     else if (split_len == 0) split = 128;
     else if (split_len % 8) return fail(PJDS_ERR_ARG, "split_len %d must be a multiple of 8", split_len);
     else split = split_len;
@@ -190,9 +202,34 @@ template <class T>
 void fill_blocks(const pjds_info &in, const int64_t *row_ptr, const int32_t *col, const T *val,
                  const int32_t *perm, const int32_t *row_len, const int64_t *offsets,
                  const int32_t *invperm, int32_t *col_p, T *val_p, const std::vector<int64_t> &bmax) {
-    const int32_t b_r = in.block_height;
+    const int32_t b_r = in.block_height, lanes = lanes_per_row(in.flags);
     const bool jd = !(in.flags & PJDS_LAYOUT_BLOCK);
     const int64_t n = in.n_rows;
+    if (lanes > 1) {
+        // T lanes per row: step q of block b is the 64-slot segment at offsets[b] + 64 q,
+        // slot r * T + t of it holds entry j = q * T + t of the block's row r
+        parallel_ranges(in.n_blocks, [&](int, int64_t b0, int64_t b1) {
+            for (int64_t b = b0; b < b1; ++b) {
+                const int64_t W = ceil_div(bmax[size_t(b)], lanes);
+                for (int64_t q = 0; q < W; ++q)
+                    for (int32_t r = 0; r < b_r; ++r)
+                        for (int32_t t = 0; t < lanes; ++t) {
+                            const int64_t i = b * b_r + r, j = q * lanes + t;
+                            const int64_t a = offsets[b] + q * kWave + r * lanes + t;
+                            if (i < n && j < row_len[i]) {
+                                const int64_t k = row_ptr[perm[i]] + j;
+                                const int32_t c = col[k];
+                                col_p[a] = invperm ? invperm[c] : c;
+                                val_p[a] = val[k];
+                            } else {
+                                col_p[a] = 0;
+                                val_p[a] = T(0);
+                            }
+                        }
+            }
+        });
+        return;
+    }
     parallel_ranges(in.n_blocks, [&](int, int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t M = bmax[size_t(b)];
@@ -242,7 +279,7 @@ int pjds_plan(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, int32_t bl
     }
     sort_rows(n_rows, n_pad, window, row_ptr, perm.data(), row_len.data());
     Plan p;
-    size_blocks(n_pad, block_height, split, row_len.data(), p);
+    size_blocks(n_pad, block_height, lanes_per_row(flags), split, row_len.data(), p);
     pjds_info info{};
     info.n_rows = n_rows;
     info.n_cols = n_cols;
@@ -291,7 +328,7 @@ int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
     }
     sort_rows(in.n_rows, in.n_pad, window, row_ptr, tperm.data(), tlen.data());
     Plan p;
-    size_blocks(in.n_pad, in.block_height, in.split_len, tlen.data(), p);
+    size_blocks(in.n_pad, in.block_height, lanes_per_row(in.flags), in.split_len, tlen.data(), p);
     if (p.nnz_stored != in.nnz_stored || p.n_chunks != in.n_chunks)
         return fail(PJDS_ERR_ARG, "info does not match the matrix (re-run pjds_plan)");
 
@@ -302,10 +339,11 @@ int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
     }
     if (in.n_rows) std::memcpy(perm, tperm.data(), sizeof(int32_t) * size_t(in.n_rows));
     std::memcpy(row_len, tlen.data(), sizeof(int32_t) * size_t(in.n_pad));
-    const int32_t b_r = in.block_height;
+    const int32_t b_r = in.block_height, lanes = lanes_per_row(in.flags);
     if (in.flags & PJDS_LAYOUT_BLOCK) {
         offsets[0] = 0;
-        for (int64_t b = 0; b < p.n_blocks; ++b) offsets[b + 1] = offsets[b] + int64_t(b_r) * p.block_max[size_t(b)];
+        for (int64_t b = 0; b < p.n_blocks; ++b)
+            offsets[b + 1] = offsets[b] + int64_t(b_r) * lanes * ceil_div(p.block_max[size_t(b)], lanes);
     } else {
         // col_start[j+1] - col_start[j] = b_r * #{blocks with M_b > j}; with a global sort
         // the block maxima do not increase, so count blocks per maximum and sweep j upward.

@@ -103,7 +103,7 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
                  const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
                  const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, double *d_alpha,
                  double *d_beta, void *d_vectors, void *d_scratch, void *stream) {
-    if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
+    if (int rc = check_product_info(info, PJDS_F64)) return rc;
     const pjds_info &in = *info;
     if (!(in.flags & PJDS_SYMMETRIC) || in.n_rows != in.n_cols)
         return fail(PJDS_ERR_ARG, "Lanczos needs a square matrix converted with PJDS_SYMMETRIC");

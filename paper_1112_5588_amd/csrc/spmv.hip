@@ -264,6 +264,46 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_lds_kernel(
     }
 }
 
+// ---- pJDS with T lanes per row --------------------------------------------------------
+// One wave per block of b_r = 64 / T sorted rows.  Lane l serves row l / T of the block and
+// takes its entries t, t + T, t + 2T, ... (t = l % T); step q of the block is the 64-slot
+// segment at block_start + 64 q, so each load of the wave is one contiguous segment for
+// every T.  Row 0 of a block is its longest row, so lane 0 has an entry at every step of the
+// block and serves as the lead lane.  The T partial sums of a row are combined by an xor
+// butterfly: every lane of the row ends with the same sum, added in a fixed order, and the
+// row's first lane writes y.
+struct LanesAddr {                      // lane slot b (= block_start + lane), step q: b + 64 q
+    int64_t start;
+    __device__ int64_t base(int64_t lane) const { return start + lane; }
+    __device__ int64_t operator()(int q, int64_t b) const { return b + int64_t(q) * kWave; }
+};
+
+template <class T, int TL>
+__global__ __launch_bounds__(kBlock) void pjds_lanes_kernel(
+    int64_t n_rows, int64_t n_blocks, const int32_t *__restrict__ row_len,
+    const int64_t *__restrict__ offsets, const int32_t *__restrict__ col_p,
+    const T *__restrict__ val_p, const int32_t *__restrict__ perm, const T *__restrict__ x, T *y,
+    Epilogue<T> epi, uint32_t flags) {
+    constexpr int BR = kWave / TL;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t b = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (b >= n_blocks) return;
+    const int t = lane % TL;
+    const int64_t i = b * BR + lane / TL;                    // < n_pad = n_blocks * BR
+    const int len = row_len[i];
+    const int steps = len > t ? (len - t + TL - 1) / TL : 0;
+    const int64_t start = offsets[b];
+    const int W = __builtin_amdgcn_readfirstlane(int((offsets[b + 1] - start) / kWave));
+    T acc = row_range_sum(int64_t(lane), int64_t(0), steps, 0, W, LanesAddr{start}, col_p, val_p,
+                          XGlobal<T>{x, 1, 0});
+#pragma unroll
+    for (int off = 1; off < TL; off <<= 1) acc += __shfl_xor(acc, off);
+    if (t == 0 && i < n_rows) {
+        const int64_t r = (flags & PJDS_Y_PERMUTED) ? i : perm[i];
+        y[r] = epi(acc, r);
+    }
+}
+
 __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
     for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) p[k] = 0;
 }
@@ -485,6 +525,27 @@ void launch_spmmv(const pjds_info &in, const int32_t *rl, const int64_t *off, co
     else launch_spmmv_v<T, JD, BR, 4>(in, rl, off, cp, vp, perm, k, lpr, X, Y, flags, s);
 }
 
+int32_t lanes_of(const pjds_info &in) { return int32_t(1) << ((in.flags & PJDS_LANES_MASK) >> PJDS_LANES_SHIFT); }
+
+template <class T>
+void launch_lanes(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp, const void *vp,
+                  const int32_t *perm, const void *x, void *y, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
+    const dim3 grid(unsigned(ceil_div(in.n_blocks, kWavesPerBlock)));
+#define PJDS_LANES_CASE(TL)                                                                              \
+    hipLaunchKernelGGL((pjds_lanes_kernel<T, TL>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_blocks, rl, off, \
+                       cp, static_cast<const T *>(vp), perm, static_cast<const T *>(x), static_cast<T *>(y),    \
+                       make_epi<T>(ea), flags)
+    switch (lanes_of(in)) {
+        case 2: PJDS_LANES_CASE(2); break;
+        case 4: PJDS_LANES_CASE(4); break;
+        case 8: PJDS_LANES_CASE(8); break;
+        case 16: PJDS_LANES_CASE(16); break;
+        case 32: PJDS_LANES_CASE(32); break;
+        default: PJDS_LANES_CASE(64); break;
+    }
+#undef PJDS_LANES_CASE
+}
+
 // Dispatch on (dtype, layout, block height) to a compile-time instantiation.
 template <template <class, bool, int> class K, class... A>
 void dispatch(int32_t dtype, bool jd, int32_t br, A &&...a) {
@@ -509,6 +570,19 @@ struct SpmvK {
     template <class... A>
     static void run(A &&...a) { launch_pjds<T, JD, BR>(a...); }
 };
+// The single-vector product for any pJDS matrix: T lanes per row, or one lane per row.
+void launch_product(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp, const void *vp,
+                    const int32_t *perm, const int32_t *sched, void *work, int32_t dtype, const void *x, void *y,
+                    const EpiArgs &ea, uint32_t flags, hipStream_t s) {
+    if (lanes_of(in) > 1) {
+        if (dtype == PJDS_F64) launch_lanes<double>(in, rl, off, cp, vp, perm, x, y, ea, flags, s);
+        else launch_lanes<float>(in, rl, off, cp, vp, perm, x, y, ea, flags, s);
+        return;
+    }
+    dispatch<SpmvK>(dtype, !(in.flags & PJDS_LAYOUT_BLOCK), in.block_height, in, rl, off, cp, vp, perm, sched, work,
+                    x, y, ea, flags, s);
+}
+
 template <class T, bool JD, int BR>
 struct SpmmvK {
     template <class... A>
@@ -518,15 +592,20 @@ struct SpmmvK {
 int check_info(const pjds_info *info, int32_t dtype) {
     if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
     if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
-    const int32_t br = info->block_height;
-    if (br != 32 && br != 64 && br != 128) return fail(PJDS_ERR_ARG, "block_height %d", br);
+    const int32_t br = info->block_height, lanes = lanes_of(*info);
+    if (lanes > 1 ? (br * lanes != kWave || !(info->flags & PJDS_LAYOUT_BLOCK) || info->n_chunks)
+                  : (br != 32 && br != 64 && br != 128))
+        return fail(PJDS_ERR_ARG, "block_height %d with %d lanes per row", br, lanes);
     if (info->n_rows < 0 || info->n_pad < info->n_rows || info->n_pad % br) return fail(PJDS_ERR_ARG, "inconsistent info");
     return PJDS_OK;
 }
 
 }  // namespace
 
+int check_product_info(const pjds_info *info, int32_t dtype) { return check_info(info, dtype); }
+
 int check_xlds(const pjds_info &in, int32_t dtype, int32_t x_halo, int32_t tile_rows) {
+    if (lanes_of(in) > 1) return fail(PJDS_ERR_UNSUPPORTED, "x staging with several lanes per row");
     const int64_t w = in.sort_window;
     if (!(in.flags & PJDS_LAYOUT_BLOCK) || w >= in.n_rows || w % kBlock)
         return fail(PJDS_ERR_ARG, "x staging needs the block layout and a sort window that is a multiple of %d", kBlock);
@@ -570,8 +649,7 @@ void launch_spmv_epi(const pjds_info &in, const int32_t *d_row_len, const int64_
                      const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
                      int32_t dtype, const void *d_x, void *d_y, const EpiArgs &ea, uint32_t flags,
                      hipStream_t s) {
-    dispatch<SpmvK>(dtype, !(in.flags & PJDS_LAYOUT_BLOCK), in.block_height, in, d_row_len, d_offsets, d_col_p,
-                    d_val_p, static_cast<const int32_t *>(nullptr), d_sched, d_work, d_x, d_y, ea, flags, s);
+    launch_product(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, d_sched, d_work, dtype, d_x, d_y, ea, flags, s);
 }
 
 }  // namespace pjds
@@ -609,9 +687,8 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
     if (info->n_chunks && (!d_sched || !d_work)) return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
-    dispatch<SpmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
-                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, EpiArgs{}, flags,
-                    static_cast<hipStream_t>(stream));
+    launch_product(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, dtype, d_x, d_y,
+                   EpiArgs{}, flags, static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv");
 }
 
@@ -629,9 +706,8 @@ int pjds_spmv_axpby(const pjds_info *info, const int32_t *d_row_len, const int64
     if (info->n_chunks && (!d_sched || !d_work)) return fail(PJDS_ERR_ARG, "long rows need d_sched and d_work");
     if (d_z && d_z != d_y && d_z == d_x) return fail(PJDS_ERR_ARG, "z may be y but not x");
     EpiArgs ea{alpha, beta, d_z, nullptr, 0.0};
-    dispatch<SpmvK>(dtype, !(info->flags & PJDS_LAYOUT_BLOCK), info->block_height, *info, d_row_len,
-                    d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, d_x, d_y, ea, flags,
-                    static_cast<hipStream_t>(stream));
+    launch_product(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, dtype, d_x, d_y,
+                   ea, flags, static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv_axpby");
 }
 
@@ -641,6 +717,7 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
                const void *d_X, void *d_Y, uint32_t flags, void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
     if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (lanes_of(*info) > 1) return fail(PJDS_ERR_UNSUPPORTED, "SpMMV with several lanes per row");
     if (k < 1) return fail(PJDS_ERR_ARG, "k = %d", k);
     const int32_t t = vectors_per_tile, vpl = vectors_per_lane;
     if (vpl != 1 && vpl != 2 && vpl != 4) return fail(PJDS_ERR_ARG, "vectors_per_lane %d: must be 1, 2 or 4", vpl);

@@ -31,9 +31,18 @@ class PjdsMatrix:
     @classmethod
     def from_csr(cls, A, block_height: int = 64, sort_window: int = 0, layout: str = "jd",
                  symmetric: bool = False, split_len: int = 0, device="cuda",
-                 keep_host: bool = False) -> "PjdsMatrix":
+                 keep_host: bool = False, lanes: int = 1) -> "PjdsMatrix":
+        """Convert CSR ``A`` (host arrays) and copy the pJDS arrays to ``device``.  ``lanes``
+        = T > 1 (a power of two, block layout) lets T lanes share each row; the block height
+        is then 64 / T whatever ``block_height`` says."""
         self = cls()
         flags = (L.PJDS_LAYOUT_BLOCK if layout == "block" else L.PJDS_LAYOUT_JD) | (L.PJDS_SYMMETRIC if symmetric else 0)
+        if lanes != 1:
+            k = int(lanes).bit_length() - 1
+            if lanes < 1 or (1 << k) != lanes or lanes > 64:
+                raise ValueError(f"lanes per row {lanes}: must be a power of two up to 64")
+            flags |= L.PJDS_LANES(k)
+            block_height = 64 // lanes
         row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
         col = np.ascontiguousarray(A.col, dtype=np.int32)
         val = np.ascontiguousarray(A.val)

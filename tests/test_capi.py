@@ -63,6 +63,9 @@ def test_plan_rejects_bad_row_ptr(args, code):
     (dict(sort_window=128, flags=L.PJDS_LAYOUT_JD), L.PJDS_ERR_ARG),      # JD needs a global sort
     (dict(flags=0x40), L.PJDS_ERR_ARG),
     (dict(split_len=12), L.PJDS_ERR_ARG),
+    (dict(block_height=32, flags=L.PJDS_LANES(1)), L.PJDS_ERR_ARG),                       # lanes need blocks
+    (dict(block_height=64, flags=L.PJDS_LAYOUT_BLOCK | L.PJDS_LANES(1)), L.PJDS_ERR_ARG),  # b_r must be 32
+    (dict(block_height=1, flags=L.PJDS_LAYOUT_BLOCK | L.PJDS_LANES(7)), L.PJDS_ERR_ARG),   # T = 128 > 64
 ])
 def test_plan_rejects_bad_options(kw, code):
     A = synth.random_csr(1000, 50, 1)
@@ -145,6 +148,20 @@ def test_device_entry_points_validate_before_touching_the_gpu():
     assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 6, 8, 4, None, None, 0, None) == L.PJDS_ERR_ARG
     assert lib.csr_spmv(10, 10, None, None, None, 0, None, None, 5, None) == L.PJDS_ERR_ARG
     assert lib.pjds_probe(3, None, None, 10, None) == L.PJDS_ERR_ARG
+
+
+def test_lanes_matrix_is_refused_by_the_products_that_do_not_take_it():
+    A = synth.random_csr(500, 500, 3, max_len=30)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 16, 128, L.PJDS_LAYOUT_BLOCK | L.PJDS_LANES(2), 0)
+    assert info.block_height == 16 and info.n_chunks == 0 and info.split_len == 0
+    lib = L.lib()
+    assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 4, 1, None, None, 0, None) == L.PJDS_ERR_UNSUPPORTED
+    assert lib.pjds_spmv_xlds(ctypes.byref(info), None, None, None, None, None, 0, None, None, 512, 512, 0, None) == L.PJDS_ERR_UNSUPPORTED
+    m = L.pjds_batch_member(info=ctypes.pointer(info))
+    out = ctypes.c_void_p()
+    assert lib.pjds_batch_create(1, ctypes.byref(m), 0, L.PJDS_Y_PERMUTED, 0, 8, ctypes.byref(out)) == L.PJDS_ERR_UNSUPPORTED
+    # the product itself takes it (and checks its arrays first)
+    assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0, None) == L.PJDS_ERR_ARG
 
 
 def test_batch_create_validates_on_the_host():

@@ -8,8 +8,9 @@ import synth
 from paper_1112_5588_amd import _lib as L
 
 
-def lib_convert(A, b_r=64, window=0, layout="jd", symmetric=False, split_len=0):
+def lib_convert(A, b_r=64, window=0, layout="jd", symmetric=False, split_len=0, lanes=1):
     flags = (L.PJDS_LAYOUT_BLOCK if layout == "block" else 0) | (L.PJDS_SYMMETRIC if symmetric else 0)
+    flags |= L.PJDS_LANES(lanes.bit_length() - 1)
     row_ptr = np.ascontiguousarray(A.row_ptr, np.int64)
     info = L.pjds_plan(A.n_rows, A.n_cols, row_ptr, b_r, window, flags, split_len)
     h = dict(perm=np.full(max(info.n_rows, 1), -7, np.int32),
@@ -30,9 +31,9 @@ def lib_convert(A, b_r=64, window=0, layout="jd", symmetric=False, split_len=0):
     return info, h
 
 
-def assert_same(A, b_r=64, window=0, layout="jd", symmetric=False, split_len=0):
-    info, h = lib_convert(A, b_r, window, layout, symmetric, split_len)
-    P = oracle.pjds_build(A, b_r, window if window else None, layout, symmetric)
+def assert_same(A, b_r=64, window=0, layout="jd", symmetric=False, split_len=0, lanes=1):
+    info, h = lib_convert(A, b_r, window, layout, symmetric, split_len, lanes)
+    P = oracle.pjds_build(A, b_r, window if window else None, layout, symmetric, lanes=lanes)
     assert info.n_pad == P["n_pad"] and info.nnz_stored == P["nnz_stored"]
     assert info.max_row_len == P["max_row_len"] and info.n_blocks == P["n_blocks"]
     for k in ("perm", "row_len", "offsets", "col_p"):
@@ -144,3 +145,19 @@ def test_conversion_is_thread_count_independent(monkeypatch):
     _, h2 = lib_convert(A, b_r=64, layout="block")
     for k in h1:
         assert np.array_equal(h1[k], h2[k]), k
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("window", [0, 64, 256])
+def test_lanes_per_row_layout(lanes, window):
+    A = synth.powerlaw(3000, seed=21, l_max=300)
+    info, h, P = assert_same(A, b_r=64 // lanes, window=window, layout="block", lanes=lanes)
+    assert info.n_chunks == 0 and info.split_len == 0
+    assert info.nnz_stored % 64 == 0
+
+
+@pytest.mark.parametrize("lanes", [2, 8])
+def test_lanes_symmetric_float32_ragged(lanes):
+    A = synth.hh_like(5001, seed=22)
+    assert_same(A, b_r=64 // lanes, layout="block", symmetric=True, lanes=lanes)
+    assert_same(A.astype(np.float32), b_r=64 // lanes, window=128, layout="block", lanes=lanes)

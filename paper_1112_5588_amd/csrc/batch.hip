@@ -30,6 +30,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 #define PJDS_UNROLL 8
 #endif
 constexpr int kUnroll = PJDS_UNROLL;
+static_assert(kUnroll == 4 || kUnroll == 8, "the clamped tail covers remainders below 8");
 
 struct Member {                    // device-side descriptor of one batch member
     const int32_t *row_len;
@@ -46,24 +47,29 @@ struct Tile {                      // wave groups [g0, g1) of member m
     int32_t m, g0, g1, pad;
 };
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
+// Rows are sorted longest first inside windows that hold whole waves, so lane 0 of a wave
+// group holds its longest row (the loop bound, and the slot that lanes past their own row
+// re-read).
+__device__ __forceinline__ int64_t wave_first(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
 }
 
 template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
-template <int U, class T, bool JD, int BR>
-__device__ __forceinline__ void steps(T &acc, int jb, int len, int64_t base, int64_t base_lead,
+// U entries from jb; with CLAMP, steps at or past m re-read step m - 1 and are masked (one
+// round trip for a ragged tail, no load past the longest row).
+template <int U, bool CLAMP, class T, bool JD, int BR>
+__device__ __forceinline__ void steps(T &acc, int jb, int m, int len, int64_t base, int64_t base_lead,
                                       const int64_t *__restrict__ off, const int32_t *__restrict__ col_p,
                                       const T *__restrict__ val_p, const T *__restrict__ x) {
     T v[U];
     int32_t c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int j = jb + u;
+        const int j = CLAMP ? min(jb + u, m - 1) : jb + u;
         const int64_t b = j < len ? base : base_lead;   // lead row: an entry at every such j
         const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
         v[u] = ld_stream(val_p + a);
@@ -75,7 +81,7 @@ __device__ __forceinline__ void steps(T &acc, int jb, int len, int64_t base, int
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const T s = __builtin_fma(v[u], xv[u], acc);
-        acc = jb + u < len ? s : acc;
+        acc = (jb + u < len && (!CLAMP || jb + u < m)) ? s : acc;
     }
 }
 
@@ -86,19 +92,21 @@ __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_pe
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + lane;
     const int len = i < M.n_pad ? M.row_len[i] : 0;
-    const int m = wave_max(len);
+    const int64_t base = JD ? i : M.offsets[(i < M.n_pad ? i : M.n_pad - 1) / BR] + (i % BR);
+    const int m = __builtin_amdgcn_readfirstlane(len);
     T acc = T(0);
     if (m > 0) {
-        const int64_t i_lead = i - lane + __builtin_ctzll(__ballot(len == m));
-        const int64_t base = JD ? i : M.offsets[i / BR] + (i % BR);
-        const int64_t base_lead = JD ? i_lead : M.offsets[i_lead / BR] + (i_lead % BR);
+        const int64_t base_lead = wave_first(base);
         const T *val_p = static_cast<const T *>(M.val_p);
         const T *x = static_cast<const T *>(M.x);
         int jb = 0;
-        for (; jb + kUnroll <= m; jb += kUnroll) steps<kUnroll, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x);
-        if (kUnroll > 4 && jb + 4 <= m) { steps<4, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x); jb += 4; }
-        if (kUnroll > 2 && jb + 2 <= m) { steps<2, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x); jb += 2; }
-        if (jb < m) steps<1, T, JD, BR>(acc, jb, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        for (; jb + kUnroll <= m; jb += kUnroll)
+            steps<kUnroll, false, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        const int r = m - jb;
+        if (r > 4) steps<8, true, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        else if (r > 2) steps<4, true, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        else if (r == 2) steps<2, false, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
+        else if (r == 1) steps<1, false, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
     }
     if (i < M.n_rows) static_cast<T *>(M.y)[y_perm ? i : M.perm[i]] = acc;
 }

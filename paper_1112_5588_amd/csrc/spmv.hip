@@ -7,10 +7,11 @@
 // segment of that block (64 values, 64 indices) is one coalesced 512 B + 256 B access per
 // step.  b_r = 32 puts two blocks in a wave, b_r = 128 spreads a block over two waves; the
 // loop bound is always the wave's own longest row, and each lane masks its arithmetic with
-// its own row length, so padding never enters a sum.  A lane past the end of its row
-// re-reads the slot of the wave's longest row (the "lead" lane) instead of its own padding
-// slot: that address and the x element it points to are already being fetched for the lead,
-// so padding costs neither HBM traffic nor extra cache lines.
+// its own row length, so padding never enters a sum.  Rows are sorted longest first inside
+// windows that hold whole waves, so lane 0 holds the wave's longest row: its length is the
+// loop bound, and a lane past the end of its own row re-reads lane 0's slot instead of its
+// own padding slot.  That address and the x element it points to are already being fetched
+// for lane 0, so padding costs neither HBM traffic nor extra cache lines.
 //
 // Streams.  Values and column indices are read exactly once per product, so they are
 // loaded non-temporally; x goes through the normal cached path (it is re-read by every
@@ -38,6 +39,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 #define PJDS_UNROLL 8
 #endif
 constexpr int kUnroll = PJDS_UNROLL;      // independent entries in flight per lane
+constexpr int kStage = 8;                 // x values in flight per thread while staging into LDS
 constexpr uint32_t kXcds = 8;
 
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
@@ -60,7 +62,17 @@ __device__ __forceinline__ int wave_max(int v) {
 template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
-// Lowest lane of the wave whose row is the longest (len == m, m > 0).
+// Rows are sorted by length, longest first, inside windows that hold whole waves, so lane 0
+// of a wave holds the wave's longest row: its length bounds the wave's loop and its slot is
+// the one lanes past their own row re-read.  Both are wave-uniform values.
+__device__ __forceinline__ int wave_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t wave_first(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// Lowest lane of the wave whose row is the longest (len == m, m > 0); for unsorted rows.
 __device__ __forceinline__ int lead_lane(int len, int m) {
     return __builtin_ctzll(__ballot(len == m));
 }
@@ -115,18 +127,20 @@ struct Epilogue {
     }
 };
 
-// U consecutive entries j in [jb, jb+U) (all below the wave's longest row) added into acc:
-// U independent value/index loads, then U gathers, then U FMAs.  A lane past the end of its
-// row reads the lead row's slot (an entry that exists for every such j) and keeps acc.
-template <int U, class T, class Addr, class XR>
-__device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base, int64_t base_lead,
+// U consecutive entries j in [jb, jb+U) added into acc: U independent value/index loads,
+// then U gathers, then U FMAs.  A lane past the end of its row reads the lead row's slot (an
+// entry that exists for every j below the wave's longest row) and keeps acc.  With CLAMP,
+// steps at or past j1 re-read step j1 - 1 and are masked, so a ragged tail of any length
+// costs one round trip to memory without a load past j1.
+template <int U, bool CLAMP, class T, class Addr, class XR>
+__device__ __forceinline__ void row_steps(T &acc, int jb, int j1, int len, int64_t base, int64_t base_lead,
                                           const Addr &addr, const int32_t *__restrict__ col_p,
                                           const T *__restrict__ val_p, const XR &xr) {
     T v[U];
     int32_t c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int j = jb + u;
+        const int j = CLAMP ? min(jb + u, j1 - 1) : jb + u;
         const int64_t a = addr(j, j < len ? base : base_lead);
         v[u] = ld_stream(val_p + a);
         c[u] = ld_stream(col_p + a);
@@ -137,35 +151,28 @@ __device__ __forceinline__ void row_steps(T &acc, int jb, int len, int64_t base,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const T s = __builtin_fma(v[u], xv[u], acc);
-        acc = jb + u < len ? s : acc;
+        acc = (jb + u < len && (!CLAMP || jb + u < j1)) ? s : acc;
     }
 }
 
 // Sum of the calling lane's row entries j in [j0, j1) (Listing 1 / Listing 2 inner loop).
-// j1 is wave-uniform and <= the wave's longest row, which is row i_lead.  Full groups of
-// kUnroll steps, then an 8/4/2/1 tail, so no load is issued past j1.
+// base is the lane's own first slot, base_lead that of the wave's longest row; j1 is
+// wave-uniform and <= that row's length.  Full groups of kUnroll steps, then one clamped
+// group for the remainder (8, 4 or 2 wide; a single step exactly).
 template <class T, class Addr, class XR>
-__device__ __forceinline__ T row_range_sum(int64_t i, int64_t i_lead, int len, int j0, int j1,
+__device__ __forceinline__ T row_range_sum(int64_t base, int64_t base_lead, int len, int j0, int j1,
                                            const Addr &addr, const int32_t *__restrict__ col_p,
                                            const T *__restrict__ val_p, const XR &xr) {
-    const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
     T acc = T(0);
     int jb = j0;
     for (; jb + kUnroll <= j1; jb += kUnroll)
-        row_steps<kUnroll>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
-    if (kUnroll > 8 && jb + 8 <= j1) {
-        row_steps<8>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
-        jb += 8;
-    }
-    if (kUnroll > 4 && jb + 4 <= j1) {
-        row_steps<4>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
-        jb += 4;
-    }
-    if (kUnroll > 2 && jb + 2 <= j1) {
-        row_steps<2>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
-        jb += 2;
-    }
-    if (jb < j1) row_steps<1>(acc, jb, len, base, base_lead, addr, col_p, val_p, xr);
+        row_steps<kUnroll, false>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    const int r = j1 - jb;
+    if (kUnroll > 8 && r > 8) row_steps<kUnroll, true>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r > 4) row_steps<8, true>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r > 2) row_steps<4, true>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r == 2) row_steps<2, false>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r == 1) row_steps<1, false>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
     return acc;
 }
 
@@ -185,11 +192,12 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
         // ---- one work item of a long wave group
         const int32_t g = sched[4 * w + 0], c = sched[4 * w + 1], nc = sched[4 * w + 2], first = sched[4 * w + 3];
         const int64_t i = int64_t(g) * kWave + lane;
+        const PjdsAddr<JD, BR> addr{offsets};
         const int len = i < n_pad ? row_len[i] : 0;
-        const int m = wave_max(len);
-        const int64_t i_lead = i - lane + lead_lane(len, m);
+        const int64_t base = addr.base(i);
+        const int m = wave_first(len);
         const int j0 = c * split_len, j1 = min(j0 + split_len, m);
-        const T part = row_range_sum(i, i_lead, len, j0, j1, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{x, 1, 0});
+        const T part = row_range_sum(base, wave_first(base), len, j0, j1, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
         partials[w * kWave + lane] = part;
         __threadfence();                                    // publish the partial sums
         int last = 0;
@@ -211,11 +219,12 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     const int64_t g = w - n_chunks;
     if (g >= n_groups) return;
     const int64_t i = g * kWave + lane;
+    const PjdsAddr<JD, BR> addr{offsets};
     const int len = i < n_pad ? row_len[i] : 0;
-    const int m = wave_max(len);
+    const int64_t base = addr.base(i);
+    const int m = wave_first(len);
     if (split_len > 0 && m > split_len) return;            // done by the work items above
-    const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : i;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, PjdsAddr<JD, BR>{offsets}, col_p, val_p, XGlobal<T>{x, 1, 0});
+    const T acc = row_range_sum(base, wave_first(base), len, 0, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
     if (i < n_rows) {
         const int64_t r = y_perm ? i : perm[i];
         y[r] = epi(acc, r);
@@ -223,44 +232,63 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
 }
 
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
-// A workgroup (4 waves) owns `tile` consecutive sorted rows (a multiple of 256).  Sorting
-// never moves a row out of its window of `window` original rows, so the tile's rows are
-// original rows inside [lo_r, hi_r), the union of the windows the tile touches.  The
-// workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into LDS once with
-// coalesced loads, then runs its rows 256 at a time; entries whose column falls in the staged
-// range read x from LDS, the others from global memory.  Rows are never split here.  Same
-// arithmetic order as pjds_spmv_kernel.
-template <class T, int BR>
-__global__ __launch_bounds__(kBlock) void pjds_spmv_lds_kernel(
+// A workgroup of NT threads (256, 512 or 1024) owns `tile` consecutive sorted rows (a
+// multiple of 256; NT = tile when tile is 512 or 1024, so every row of the tile runs at
+// once).  Sorting never moves a row out of its window of `window` original rows, so the
+// tile's rows are original rows inside [lo_r, hi_r), the union of the windows the tile
+// touches.  The workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into
+// LDS once with coalesced loads, then runs its rows NT at a time; entries whose column falls
+// in the staged range read x from LDS, the others from global memory.  Rows are never split
+// here.  Same arithmetic order as pjds_spmv_kernel.
+template <class T, int BR, int NT>
+__global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
     int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
     const int32_t *__restrict__ perm, const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
-    const int lane = threadIdx.x & (kWave - 1);
     const int64_t r0 = int64_t(logical_block(flags)) * tile;         // first sorted row of the tile
     const int64_t lo_r = r0 / window * window;
     const int64_t hi_r = (r0 + tile + window - 1) / window * window;
     const int64_t lo = lo_r - halo > 0 ? lo_r - halo : 0;
     const int64_t hi = hi_r + halo < n_cols ? hi_r + halo : n_cols;
-    for (int64_t c = lo + threadIdx.x; c < hi; c += kBlock) xs[c - lo] = x[c];
+    // The first rows' lengths and block offsets go out before the copy of x, so their latency
+    // overlaps it (the barrier waits for LDS traffic only).  Rows past n_pad (length 0)
+    // address the last real row, so the offsets are never read out of range.
+    const PjdsAddr<false, BR> addr{offsets};
+    int64_t i = r0 + threadIdx.x;
+    int len = i < n_pad ? row_len[i] : 0;
+    int64_t base = addr.base(i < n_pad ? i : n_pad - 1);
+    // copy x[lo, hi) with kStage independent loads in flight per thread
+    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
+        T v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int64_t c = c0 + int64_t(u) * NT;
+            v[u] = c < hi ? x[c] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int64_t c = c0 + int64_t(u) * NT;
+            if (c < hi) xs[c - lo] = v[u];
+        }
+    }
     __syncthreads();
     const XStaged<T> xr{x, xs, lo, uint32_t(hi > lo ? hi - lo : 0)};
     const bool y_perm = flags & PJDS_Y_PERMUTED;
-    for (int64_t rb = r0; rb < r0 + tile && rb < n_pad; rb += kBlock) {
-        const int64_t i = rb + threadIdx.x;
-        const int len = i < n_pad ? row_len[i] : 0;
-        const int m = wave_max(len);
-        // rows past n_pad (length 0) address the last real row, so the block offsets are
-        // never read out of range
-        const int64_t ia = i < n_pad ? i : n_pad - 1;
-        const int64_t i_lead = m > 0 ? i - lane + lead_lane(len, m) : ia;
-        const T acc = row_range_sum(ia, i_lead, len, 0, m, PjdsAddr<false, BR>{offsets}, col_p, val_p, xr);
+    for (int64_t rb = r0;;) {
+        const int m = wave_first(len);
+        const T acc = row_range_sum(base, wave_first(base), len, 0, m, addr, col_p, val_p, xr);
         if (i < n_rows) {
             const int64_t r = y_perm ? i : perm[i];
             y[r] = epi(acc, r);
         }
+        rb += NT;
+        if (rb >= r0 + tile || rb >= n_pad) break;
+        i = rb + threadIdx.x;
+        len = i < n_pad ? row_len[i] : 0;
+        base = addr.base(i < n_pad ? i : n_pad - 1);
     }
 }
 
@@ -294,8 +322,7 @@ __global__ __launch_bounds__(kBlock) void pjds_lanes_kernel(
     const int steps = len > t ? (len - t + TL - 1) / TL : 0;
     const int64_t start = offsets[b];
     const int W = __builtin_amdgcn_readfirstlane(int((offsets[b + 1] - start) / kWave));
-    T acc = row_range_sum(int64_t(lane), int64_t(0), steps, 0, W, LanesAddr{start}, col_p, val_p,
-                          XGlobal<T>{x, 1, 0});
+    T acc = row_range_sum(start + lane, start, steps, 0, W, LanesAddr{start}, col_p, val_p, XGlobal<T>{x, 1, 0});
 #pragma unroll
     for (int off = 1; off < TL; off <<= 1) acc += __shfl_xor(acc, off);
     if (t == 0 && i < n_rows) {
@@ -345,12 +372,12 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
     const int vc = v < k ? v : k - VPL;
     const int64_t i = w * R + lane / LPR;
     const int len = i < n_pad ? row_len[i] : 0;
-    const int m = wave_max(len);
+    const int m = wave_first(len);
     V acc;
 #pragma unroll
     for (int q = 0; q < VPL; ++q) reinterpret_cast<T *>(&acc)[q] = T(0);
     if (m > 0) {
-        const int64_t i_lead = w * R + lead_lane(len, m) / LPR;
+        const int64_t i_lead = w * R;                      // the wave's first row is its longest
         const PjdsAddr<JD, BR> addr{offsets};
         const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
         for (int jb = 0; jb < m; jb += U) {
@@ -393,7 +420,8 @@ __global__ __launch_bounds__(kBlock) void ellr_spmv_kernel(
     const int m = wave_max(len);
     // lanes past their row read the slot of the wave's longest row (never padding)
     const int64_t i_lead = m > 0 ? i - (threadIdx.x & (kWave - 1)) + lead_lane(len, m) : 0;
-    const T acc = row_range_sum(i, i_lead, len, 0, m, EllrAddr{n_pad}, col_e, val_e, XGlobal<T>{x, 1, 0});
+    const T acc = row_range_sum(EllrAddr{n_pad}.base(i), i_lead, len, 0, m, EllrAddr{n_pad}, col_e, val_e,
+                                XGlobal<T>{x, 1, 0});
     if (i < n_rows) y[i] = acc;
 }
 
@@ -628,18 +656,25 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
     const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), in.n_cols);
     const dim3 grid(unsigned(ceil_div(in.n_pad, tile)));
     const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
+    // a workgroup as wide as the tile when the tile is 512 or 1024 rows, else 256 threads
+    const int nt = tile % 1024 == 0 ? 1024 : tile % 512 == 0 ? 512 : kBlock;
     auto go = [&](auto tag) {
         using T = decltype(tag);
         const int br = in.block_height;
-#define PJDS_XLDS_CASE(B)                                                                                \
-        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B>), grid, dim3(kBlock), lds, s, in.n_rows, in.n_cols,   \
+#define PJDS_XLDS_LAUNCH(B, N)                                                                            \
+        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B, N>), grid, dim3(N), lds, s, in.n_rows, in.n_cols,     \
                            in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,                  \
                            static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
                            static_cast<T *>(d_y), make_epi<T>(ea), flags)
-        if (br == 32) PJDS_XLDS_CASE(32);
-        else if (br == 64) PJDS_XLDS_CASE(64);
-        else PJDS_XLDS_CASE(128);
+#define PJDS_XLDS_CASE(B)                                                                                 \
+        if (nt == 1024) PJDS_XLDS_LAUNCH(B, 1024);                                                         \
+        else if (nt == 512) PJDS_XLDS_LAUNCH(B, 512);                                                      \
+        else PJDS_XLDS_LAUNCH(B, kBlock)
+        if (br == 32) { PJDS_XLDS_CASE(32); }
+        else if (br == 64) { PJDS_XLDS_CASE(64); }
+        else { PJDS_XLDS_CASE(128); }
 #undef PJDS_XLDS_CASE
+#undef PJDS_XLDS_LAUNCH
     };
     if (dtype == PJDS_F64) go(double{});
     else go(float{});

@@ -155,7 +155,7 @@ def main() -> int:
     ap.add_argument("--layout", default="block", choices=["jd", "block"])
     ap.add_argument("--mode", default="y_permuted", choices=["y_permuted", "scatter", "symmetric"])
     ap.add_argument("--split-len", type=int, default=0)
-    ap.add_argument("--sort-window", type=int, default=256, help="0 = global sort")
+    ap.add_argument("--sort-window", type=int, default=512, help="0 = global sort")
     ap.add_argument("--xcd-remap", action="store_true")
     ap.add_argument("--x-halo", type=int, default=512,
                     help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0); -1: x through the caches")
@@ -353,7 +353,7 @@ def main() -> int:
         xo = torch.from_numpy(x_np).to("cuda", tdt)
         t_cat = autotune.time_all(A, x=xo)
         lds = {}
-        for sw, halo, tile in ((256, 512, 512), (512, 1024, 512), (1024, 1024, 1024)):
+        for sw, halo, tile in ((256, 512, 512), (512, 512, 512), (512, 1024, 512), (1024, 1024, 1024)):
             Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
             yw = torch.empty(n, dtype=tdt, device="cuda")
             lds[f"pjds_b64_w{sw}_lds{halo}_t{tile}"] = autotune.time_median(

@@ -168,6 +168,8 @@ def _stream(s):
 
 def _dtype_code(dt) -> int:
     name = str(dt).replace("torch.", "")
+    if name.startswith("<class"):                 # numpy scalar types such as np.float64
+        name = np.dtype(dt).name
     if name in ("float64", "double"):
         return PJDS_F64
     if name in ("float32", "float"):

@@ -222,7 +222,9 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
  *   w = w - alpha_j v_j;  beta_{j+1} = ||w||;  v_{j+1} = w / beta_{j+1}.
  * FP64 only.  d_v0 [n_rows] is the start vector in the permuted basis (x_p[i] = x[perm[i]]).
  * Outputs (device): d_alpha [steps], d_beta [steps + 1] (beta_0 = 0).  The scalars stay on the
- * device; nothing synchronises with the host, so the call may be captured in a graph.
+ * device; nothing synchronises with the host, so the call may be captured in a graph.  The
+ * Lanczos vectors are held unnormalised (v_j = u_j / s_j, the 1/s_j factors applied inside
+ * the product and the updates), which saves the rescaling pass; d_v0 is only read.
  * x_halo >= 0 uses the LDS-staged product (pjds_spmv_xlds's conditions), otherwise the plain
  * one (d_sched/d_work as for pjds_spmv).  d_vectors and d_scratch are device buffers of the
  * sizes pjds_lanczos_workspace reports (three vectors; reduction partials).  A zero beta

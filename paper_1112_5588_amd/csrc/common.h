@@ -33,6 +33,7 @@ struct EpiArgs {
     const void *z = nullptr;
     const void *beta_dev = nullptr;   // if set, b = bscale * (*beta_dev) read on the device
     double bscale = 0.0;
+    const void *alpha_dev = nullptr;  // if set, the factor of A x is *alpha_dev, read on the device
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -3,16 +3,21 @@
 //
 // The paper motivates pJDS by Krylov solvers that permute once before the iteration and
 // once after it (Sect. 2.1).  With a matrix converted with PJDS_SYMMETRIC the product maps
-// permuted vectors to permuted vectors, so the whole recurrence stays in that basis:
+// permuted vectors to permuted vectors, so the whole recurrence stays in that basis.  The
+// Lanczos vectors are kept unnormalised, v_j = u_j / s_j (s_0 = |v|, s_j = beta_j), so no
+// pass rescales a vector:
 //
-//     w = A v_j - beta_j v_{j-1}              one pJDS product, the subtraction in its epilogue
-//     alpha_j = w . v_j                       deterministic two-stage reduction
-//     w = w - alpha_j v_j;  s = w . w         one pass
-//     beta_{j+1} = sqrt(s);  v_{j+1} = w / beta_{j+1}
+//     w = (1/s_j) A u_j - (beta_j / s_{j-1}) u_{j-1}   one pJDS product, both factors applied
+//                                                     in its epilogue
+//     alpha_j = (w . u_j) / s_j                       deterministic two-stage reduction
+//     w = w - (alpha_j / s_j) u_j;  t = w . w         one pass
+//     beta_{j+1} = sqrt(t);  u_{j+1} = w
 //
-// The scalars alpha and beta stay in device memory and every kernel reads them there, so a
-// step needs no host synchronisation and a sequence of steps can be captured in a graph.
-// Reductions use a fixed grid and fixed summation trees: results are reproducible bit for bit.
+// Every scalar stays in device memory and every kernel reads it there, so a step needs no
+// host synchronisation and a sequence of steps can be captured in a graph.  Reductions use a
+// fixed grid and fixed summation trees: results are reproducible bit for bit.  Six vector
+// passes per step besides the product's own x and y traffic (z read, w and u_j read twice,
+// w written once).
 #include <algorithm>
 #include <cmath>
 
@@ -46,13 +51,14 @@ __global__ __launch_bounds__(kRedThreads) void dot_partial_kernel(int64_t n, con
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// w = w - (*alpha) v, and partial[b] = this block's share of w . w (new w)
+// w = w - (*alpha) (*scale) v, and partial[b] = this block's share of w . w (new w)
 __global__ __launch_bounds__(kRedThreads) void axpy_norm_partial_kernel(int64_t n, double *__restrict__ w,
                                                                         const double *__restrict__ v,
                                                                         const double *__restrict__ alpha,
+                                                                        const double *__restrict__ scale,
                                                                         double *__restrict__ partial) {
     __shared__ double red[kRedThreads];
-    const double a = alpha[0];
+    const double a = alpha[0] * scale[0];
     double s = 0.0;
     for (int64_t i = blockIdx.x * int64_t(kRedThreads) + threadIdx.x; i < n; i += int64_t(kRedBlocks) * kRedThreads) {
         const double wi = __builtin_fma(-a, v[i], w[i]);
@@ -63,27 +69,35 @@ __global__ __launch_bounds__(kRedThreads) void axpy_norm_partial_kernel(int64_t 
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// out[0] = sum of the kRedBlocks partials (fixed tree), or its square root
-__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, double *out, int sqrt_it) {
+// Sum of the kRedBlocks partials (fixed tree), then one of
+//   kAlpha:  out[0] = sum * inv_s[0]                           (alpha_j = (w . u_j) / s_j)
+//   kBeta:   b = sqrt(sum); out[0] = b; inv_next[0] = 1 / b;   (beta_{j+1}, 1 / s_{j+1},
+//            zc_next[0] = b * inv_s[0]                          beta_{j+1} / s_j)
+//   kNorm:   inv_next[0] = 1 / sqrt(sum)                       (1 / s_0)
+enum FinishMode { kAlpha = 0, kBeta = 1, kNorm = 2 };
+__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, int mode,
+                                                             const double *inv_s, double *out, double *inv_next,
+                                                             double *zc_next) {
     __shared__ double red[kRedThreads];
     double s = 0.0;
     for (int q = threadIdx.x; q < kRedBlocks; q += kRedThreads) s += partial[q];
     const double t = block_sum(s, red);
-    if (threadIdx.x == 0) out[0] = sqrt_it ? sqrt(t) : t;
-}
-
-// dst = src / (*d)   (src may be dst)
-__global__ void scale_kernel(int64_t n, const double *src, const double *__restrict__ d, double *dst) {
-    const double q = d[0];
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        dst[i] = src[i] / q;
+    if (threadIdx.x != 0) return;
+    if (mode == kAlpha) {
+        out[0] = t * inv_s[0];
+    } else if (mode == kBeta) {
+        const double b = sqrt(t);
+        out[0] = b;
+        inv_next[0] = 1.0 / b;
+        zc_next[0] = b * inv_s[0];
+    } else {
+        inv_next[0] = 1.0 / sqrt(t);
+    }
 }
 
 __global__ void fill_kernel(int64_t n, double *p, double v) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
-
-unsigned elem_grid(int64_t n) { return unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n, 256), 1), 4096)); }
 
 }  // namespace
 }  // namespace pjds
@@ -121,33 +135,40 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     double *V = static_cast<double *>(d_vectors);
     double *part = static_cast<double *>(d_scratch);
-    double *norm0 = part + kRedBlocks;
-    const unsigned eg = elem_grid(n);
-    // v_0 = v / ||v||, v_{-1} = 0, beta_0 = 0
+    // device scalars, two slots each (step j reads slot j % 2, its last kernel writes the other)
+    double *inv_s = part + kRedBlocks;          // 1 / s_j
+    double *zc = inv_s + 2;                     // beta_j / s_{j-1}
+    // 1 / s_0 = 1 / |v|, beta_0 = 0
     hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, norm0, 1);
-    hipLaunchKernelGGL(scale_kernel, dim3(eg), dim3(256), 0, s, n, d_v0, norm0, V);
-    hipLaunchKernelGGL(fill_kernel, dim3(eg), dim3(256), 0, s, n, V + 2 * n, 0.0);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kNorm), nullptr, nullptr, inv_s,
+                       nullptr);
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, int64_t(1), d_beta, 0.0);
     for (int32_t j = 0; j < steps; ++j) {
-        double *vj = V + int64_t(j % 3) * n, *vprev = V + int64_t((j + 2) % 3) * n, *w = V + int64_t((j + 1) % 3) * n;
-        // w = A v_j - beta_j v_{j-1}
+        // u_0 is the caller's v (read only); then w of step j lands in V[(j + 1) % 3], which
+        // held u_{j-2}
+        const double *uj = j == 0 ? d_v0 : V + int64_t(j % 3) * n;
+        const double *uprev = j == 0 ? nullptr : j == 1 ? d_v0 : V + int64_t((j - 1) % 3) * n;
+        double *w = V + int64_t((j + 1) % 3) * n;
+        double *inv_j = inv_s + (j & 1), *inv_n = inv_s + ((j + 1) & 1);
+        // w = (1/s_j) A u_j - (beta_j / s_{j-1}) u_{j-1}
         EpiArgs ea;
-        ea.alpha = 1.0;
-        ea.z = vprev;
-        ea.beta_dev = d_beta + j;
+        ea.alpha_dev = inv_j;
+        ea.z = uprev;
+        ea.beta_dev = zc + (j & 1);
         ea.bscale = -1.0;
         if (x_halo >= 0)
-            launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, vj, w, x_halo, tile_rows, ea,
+            launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, uj, w, x_halo, tile_rows, ea,
                         PJDS_Y_PERMUTED, s);
         else
-            launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, vj, w, ea,
+            launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, uj, w, ea,
                             PJDS_Y_PERMUTED, s);
-        hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, vj, part);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, d_alpha + j, 0);
-        hipLaunchKernelGGL(axpy_norm_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, vj, d_alpha + j, part);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, d_beta + j + 1, 1);
-        hipLaunchKernelGGL(scale_kernel, dim3(eg), dim3(256), 0, s, n, w, d_beta + j + 1, w);
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kAlpha), inv_j, d_alpha + j,
+                           nullptr, nullptr);
+        hipLaunchKernelGGL(axpy_norm_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, d_alpha + j,
+                           inv_j, part);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kBeta), inv_j, d_beta + j + 1,
+                           inv_n, zc + ((j + 1) & 1));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(PJDS_ERR_HIP, "pjds_lanczos: %s", hipGetErrorString(e));

@@ -120,10 +120,12 @@ struct Epilogue {
     const T *z;
     const T *beta_dev;
     T bscale;
+    const T *alpha_dev;                 // if set, alpha = *alpha_dev
     __device__ T operator()(T acc, int64_t r) const {
-        if (!z) return alpha * acc;
+        const T a = alpha_dev ? alpha_dev[0] : alpha;
+        if (!z) return a * acc;
         const T b = beta_dev ? bscale * beta_dev[0] : beta;
-        return __builtin_fma(b, z[r], alpha * acc);
+        return __builtin_fma(b, z[r], a * acc);
     }
 };
 
@@ -489,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__rest
 template <class T>
 Epilogue<T> make_epi(const EpiArgs &a) {
     return Epilogue<T>{T(a.alpha), T(a.beta), static_cast<const T *>(a.z), static_cast<const T *>(a.beta_dev),
-                       T(a.bscale)};
+                       T(a.bscale), static_cast<const T *>(a.alpha_dev)};
 }
 
 int launch_status(const char *what) {

@@ -164,9 +164,10 @@ class ResultStore:
             f.write(json.dumps(record) + "\n")
 
 
-def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[tuple[int, int], dict[tuple[int, int], float]]:
-    """(vectors per tile, vectors per lane) for k right-hand sides: the fastest pair with a
-    tile of at most 2k vectors."""
+def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[tuple[int, int, bool], dict[tuple[int, int, bool], float]]:
+    """(vectors per tile, vectors per lane, XCD renumbering) for k right-hand sides: the fastest
+    combination with a tile of at most 2k vectors.  Renumbering helps SpMMV more than the
+    single product because each XCD's L2 then keeps the rows of X that neighbouring rows share."""
     import synth
     X = torch.from_numpy(synth.dense_x(M.n_cols, 4, k=k).reshape(M.n_cols, k)).to(M.device, M.dtype)
     Y = torch.empty((M.n_rows, k), dtype=M.dtype, device=M.device)
@@ -178,8 +179,10 @@ def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[tuple[int, int], d
             t = lpr * vpl
             if t > 1 and t // 2 >= k:
                 continue
-            t_ms[(t, vpl)] = time_median(
-                lambda: M.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True), reps, 1)
+            for remap in (False, True):
+                t_ms[(t, vpl, remap)] = time_median(
+                    lambda: M.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True,
+                                    xcd_remap=remap), reps, 1)
     return min(t_ms, key=t_ms.get), t_ms
 
 

@@ -145,7 +145,8 @@ class PjdsMatrix:
         return y
 
     def spmmv(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int | None = None,
-              y_permuted: bool = False, stream=None, vectors_per_lane: int | None = None) -> torch.Tensor:
+              y_permuted: bool = False, stream=None, vectors_per_lane: int | None = None,
+              xcd_remap: bool = False) -> torch.Tensor:
         k = X.shape[1]
         if vectors_per_tile is None:
             vectors_per_tile = min(32, 1 << (k - 1).bit_length())
@@ -153,7 +154,7 @@ class PjdsMatrix:
             vectors_per_lane = next(v for v in (4, 2, 1) if k % v == 0 and vectors_per_tile % v == 0)
         if Y is None:
             Y = torch.empty((self.info.n_rows, k), dtype=self.dtype, device=self.device)
-        flags = L.PJDS_Y_PERMUTED if y_permuted else 0
+        flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
         d = self.d
         L.pjds_spmmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], k,
                      vectors_per_tile, X, Y, flags, stream, vectors_per_lane)

@@ -218,6 +218,19 @@ def test_spmmv_random(b_r, layout):
         assert oracle.rel_l2(Y, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("window", [256, 4096])
+def test_spmmv_xcd_renumbering_is_bitwise_identical(window):
+    # renumbering workgroups changes which XCD runs a tile, not the arithmetic
+    A = synth.hh_like(100003, seed=18)
+    X = dev(synth.dense_x(A.n_cols, 42, k=8).reshape(A.n_cols, 8))
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=window, keep_host=True)
+    Y0 = M.spmmv(X, vectors_per_tile=8, vectors_per_lane=4, y_permuted=True)
+    Y1 = M.spmmv(X, vectors_per_tile=8, vectors_per_lane=4, y_permuted=True, xcd_remap=True)
+    assert torch.equal(Y0, Y1)
+    ref = oracle.csr_spmmv(A, host(X))[M.host["perm"]]
+    assert oracle.rel_l2(host(Y1), ref) <= 1e-12
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 @pytest.fixture(scope="module")

@@ -29,8 +29,8 @@ def test_autotune_picks_the_fastest_configuration():
 def test_spmmv_and_batch_tuning_return_catalog_values():
     A = synth.laplacian_2d(128)
     M = PjdsMatrix.from_csr(A)
-    (t, vpl), times = autotune.tune_spmmv(M, 8)
-    assert t in (1, 2, 4, 8, 16) and vpl in (1, 2, 4) and times[(t, vpl)] == min(times.values())
+    (t, vpl, remap), times = autotune.tune_spmmv(M, 8)
+    assert t in (1, 2, 4, 8, 16) and vpl in (1, 2, 4) and times[(t, vpl, remap)] == min(times.values())
     mats = [PjdsMatrix.from_csr(synth.banded_stratified(n, 1000 + k), split_len=-1) for k, n in enumerate((1000, 5000, 20000))]
     xs = [torch.from_numpy(synth.dense_x(M_.n_cols, 7)).cuda() for M_ in mats]
     ys = [torch.empty(M_.n_rows, dtype=torch.float64, device="cuda") for M_ in mats]

@@ -334,24 +334,26 @@ def main() -> int:
         ms_nr = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=True), 50, 5)
         extra["pjds_scatter_y"] = {"ms": round(ms_s, 5)}
         extra["pjds_xcd_remap"] = {"ms": round(ms_nr, 5)}
-        # many right-hand sides on the same matrix (block layout, window 4096, tuned tile and
-        # XCD renumbering: each XCD's L2 then keeps the rows of X that neighbouring rows share):
-        # effective GFLOP/s vs the headline single-vector product
-        spmmv = {"plain_gflops": round(gflops, 2), "sort_window": 4096}
+        # many right-hand sides on the same matrix: the tile shape and XCD renumbering tuned
+        # per k on two sort windows (256 keeps shared rows of X close; 4096 with renumbering lets
+        # each XCD's L2 keep them); effective GFLOP/s vs the headline single-vector product
+        spmmv = {"plain_gflops": round(gflops, 2)}
         from paper_1112_5588_amd import autotune as _at
-        Mk = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=4096)
-        for k in (4, 8, 16, 32):
-            (t, vpl, rmp), _ = _at.tune_spmmv(Mk, k, reps=3)
-            X = torch.from_numpy(synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)).to("cuda", tdt)
-            Y = torch.empty((n, k), dtype=tdt, device="cuda")
-            ms_k = time_launches(lambda: Mk.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True,
-                                                  xcd_remap=rmp), 20, 3)
-            spmmv[f"k{k}"] = {"tile": t, "vectors_per_lane": vpl, "xcd_remap": rmp, "ms": round(ms_k, 5),
-                              "gflops": round(2 * k * nnz / ms_k / 1e6, 2),
-                              "over_plain": round(2 * k * nnz / ms_k / 1e6 / gflops, 2)}
-            del X, Y
+        for sw_k in (256, 4096):
+            Mk = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw_k)
+            for k in (4, 8, 16, 32):
+                (t, vpl, rmp), _ = _at.tune_spmmv(Mk, k, reps=3)
+                X = torch.from_numpy(synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)).to("cuda", tdt)
+                Y = torch.empty((n, k), dtype=tdt, device="cuda")
+                ms_k = time_launches(lambda: Mk.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl,
+                                                      y_permuted=True, xcd_remap=rmp), 20, 3)
+                if f"k{k}" not in spmmv or ms_k < spmmv[f"k{k}"]["ms"]:
+                    spmmv[f"k{k}"] = {"sort_window": sw_k, "tile": t, "vectors_per_lane": vpl, "xcd_remap": rmp,
+                                      "ms": round(ms_k, 5), "gflops": round(2 * k * nnz / ms_k / 1e6, 2),
+                                      "over_plain": round(2 * k * nnz / ms_k / 1e6 / gflops, 2)}
+                del X, Y
+            del Mk
         extra["spmmv"] = spmmv
-        del Mk
         # exhaustive autotuner on this matrix: every catalog configuration, plus x in LDS
         from paper_1112_5588_amd import autotune
         log("autotuner leg")

@@ -127,6 +127,14 @@ struct Epilogue {
         const T b = beta_dev ? bscale * beta_dev[0] : beta;
         return __builtin_fma(b, z[r], a * acc);
     }
+    // y[r] = (*this)(acc, r).  The plain product's y is written once and not read back by the
+    // kernel, so it is stored non-temporally (keeps the caches for x); a solver's update, whose
+    // result the next kernel reads at once, is stored normally.
+    __device__ void store(T *y, int64_t r, T acc) const {
+        const T v = (*this)(acc, r);
+        if (!z && !alpha_dev) __builtin_nontemporal_store(v, y + r);
+        else y[r] = v;
+    }
 };
 
 // U consecutive entries j in [jb, jb+U) added into acc: U independent value/index loads,
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
             for (int q = 1; q < nc; ++q) s += pp[int64_t(q) * kWave];
             if (i < n_rows) {
                 const int64_t r = y_perm ? i : perm[i];
-                y[r] = epi(s, r);
+                epi.store(y, r, s);
             }
             if (lane == 0) counters[first] = 0;             // ready for the next product
         }
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     const T acc = row_range_sum(base, wave_first(base), len, 0, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
     if (i < n_rows) {
         const int64_t r = y_perm ? i : perm[i];
-        y[r] = epi(acc, r);
+        epi.store(y, r, acc);
     }
 }
 
@@ -284,7 +292,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
         const T acc = row_range_sum(base, wave_first(base), len, 0, m, addr, col_p, val_p, xr);
         if (i < n_rows) {
             const int64_t r = y_perm ? i : perm[i];
-            y[r] = epi(acc, r);
+            epi.store(y, r, acc);
         }
         rb += NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
@@ -329,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void pjds_lanes_kernel(
     for (int off = 1; off < TL; off <<= 1) acc += __shfl_xor(acc, off);
     if (t == 0 && i < n_rows) {
         const int64_t r = (flags & PJDS_Y_PERMUTED) ? i : perm[i];
-        y[r] = epi(acc, r);
+        epi.store(y, r, acc);
     }
 }
 
@@ -407,8 +415,8 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
             }
         }
     }
-    if (i < n_rows && v < k)
-        *reinterpret_cast<V *>(Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v) = acc;
+    if (i < n_rows && v < k)            // Y is written once: stored non-temporally
+        __builtin_nontemporal_store(acc, reinterpret_cast<V *>(Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v));
 }
 
 // ---- ELLPACK-R, Listing 1 -------------------------------------------------------------

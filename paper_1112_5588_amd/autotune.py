@@ -32,6 +32,8 @@ class Config:
     split_len: int = 0
     xcd_remap: bool = False
     variant: int = 1            # CSR lanes per row
+    x_halo: int = -1            # >= 0: x staged in LDS (pjds_spmv_xlds) with this halo
+    tile_rows: int = 0          # rows per workgroup of the LDS path
 
     def storage_key(self):
         if self.fmt == "pjds":
@@ -57,6 +59,8 @@ CATALOG: tuple[Config, ...] = (
     Config("csr_v1", "csr", variant=1),
     Config("csr_v4", "csr", variant=4),
     Config("csr_v16", "csr", variant=16),
+    Config("pjds_b64_w256_lds512", "pjds", 64, "block", 256, x_halo=512, tile_rows=512),
+    Config("pjds_b64_w512_lds512", "pjds", 64, "block", 512, x_halo=512, tile_rows=512),
 )
 CONFIG_NAMES = tuple(c.name for c in CATALOG)
 DEFAULT = 0
@@ -96,7 +100,20 @@ def _build(A, cfg: Config, device):
     return CsrMatrix.from_csr(A, device=device)
 
 
+def _lds_fits(obj, cfg: Config) -> bool:
+    """Whether the LDS path takes this matrix: a sort window (not a global sort) that is a
+    multiple of 256, and the staged x range within 64 KiB."""
+    w, n = obj.info.sort_window, obj.info.n_rows
+    esz = 8 if obj.dtype == torch.float64 else 4
+    return w < n and w % 256 == 0 and min(max(cfg.tile_rows, w) + 2 * cfg.x_halo, obj.info.n_cols) * esz <= 65536
+
+
 def _runner(obj, cfg: Config, x, y):
+    if cfg.fmt == "pjds" and cfg.x_halo >= 0:
+        if not _lds_fits(obj, cfg):
+            return None
+        return lambda: obj.spmv_xlds(x, y, x_halo=cfg.x_halo, tile_rows=cfg.tile_rows, y_permuted=True,
+                                     xcd_remap=cfg.xcd_remap)
     if cfg.fmt == "pjds":
         return lambda: obj.spmv(x, y, y_permuted=True, xcd_remap=cfg.xcd_remap)
     if cfg.fmt == "ellr":
@@ -119,7 +136,8 @@ def time_all(A, x: torch.Tensor | None = None, configs=CATALOG, reps: int = 7, w
     for _, cfgs in groups.items():
         obj = _build(A, cfgs[0], device)
         for c in cfgs:
-            out[c.name] = float("inf") if obj is None else time_median(_runner(obj, c, x, y), reps, warmup)
+            run = None if obj is None else _runner(obj, c, x, y)
+            out[c.name] = float("inf") if run is None else time_median(run, reps, warmup)
         del obj
     return out
 
@@ -162,6 +180,14 @@ class ResultStore:
         self.records[(record["key"], record["device"])] = record
         with open(self.path, "a") as f:
             f.write(json.dumps(record) + "\n")
+
+    def rewrite(self) -> None:
+        """Rewrite the file with one line per record (later lines of a key replace earlier)."""
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            for r in self.records.values():
+                f.write(json.dumps(r) + "\n")
+        os.replace(tmp, self.path)
 
 
 def tune_spmmv(M: PjdsMatrix, k: int, reps: int = 5) -> tuple[tuple[int, int, bool], dict[tuple[int, int, bool], float]]:

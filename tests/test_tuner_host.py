@@ -87,3 +87,20 @@ def test_ellr_fit_from_features():
     X[1, 13] = 12.0         # 4096 x nnz
     ok = tuner.ellr_fits(X, np.array([1e6, 1e6]))
     assert ok.tolist() == [True, False]
+
+
+def test_store_update_merges_and_compacts(tmp_path):
+    from paper_1112_5588_amd import tuner
+    p = str(tmp_path / "s.jsonl")
+    st = autotune.ResultStore(p)
+    st.add({"key": "1", "device": "d", "nnz": 5, "features": [0.0] * 24, "times_ms": {"a": 1.0}})
+    st.add({"key": "2", "device": "d", "nnz": 5, "features": [0.0] * 24, "times_ms": {"a": 2.0}})
+    rec = dict(st.records[("1", "d")])
+    rec["times_ms"] = {**rec["times_ms"], "b": 3.0}
+    st.add(rec)
+    recs = tuner.load_records(p)
+    assert [r["key"] for r in recs] == ["1", "2"] and recs[0]["times_ms"] == {"a": 1.0, "b": 3.0}
+    assert len(open(p).read().splitlines()) == 3
+    st.rewrite()
+    assert len(open(p).read().splitlines()) == 2
+    assert tuner.load_records(p) == recs

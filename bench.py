@@ -354,6 +354,39 @@ def main() -> int:
                 del X, Y
             del Mk
         extra["spmmv"] = spmmv
+        # the small case (128 x 128 Laplacian): one SpMMV launch against k single products,
+        # launched one by one and replayed from a captured graph
+        L1 = synth.laplacian_2d(128)
+        M1 = PjdsMatrix.from_csr(L1, block_height=64)
+        small = {}
+        for k in (1, 4, 8, 16, 32):
+            Xk = torch.from_numpy(synth.dense_x(L1.n_cols, 4, k=k).reshape(L1.n_cols, k)).cuda()
+            Yk = torch.empty((L1.n_rows, k), dtype=torch.float64, device="cuda")
+            (t, vpl, rmp), _ = _at.tune_spmmv(M1, k, reps=5)
+            ms_mm = time_launches(lambda: M1.spmmv(Xk, Yk, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True,
+                                                   xcd_remap=rmp), 200, 20)
+            xs = [Xk[:, v].contiguous() for v in range(k)]
+            ys = [torch.empty(L1.n_rows, dtype=torch.float64, device="cuda") for _ in range(k)]
+
+            def singles():
+                for v in range(k):
+                    M1.spmv(xs[v], ys[v], y_permuted=True)
+            ms_sep = time_launches(singles, 200, 20)
+            g1 = torch.cuda.CUDAGraph()
+            cs1 = torch.cuda.Stream()
+            cs1.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs1):
+                with torch.cuda.graph(g1, stream=cs1):
+                    singles()
+            torch.cuda.current_stream().wait_stream(cs1)
+            ms_gr = time_launches(g1.replay, 200, 20)
+            f = 2 * k * L1.nnz / 1e6
+            small[f"k{k}"] = {"spmmv_ms": round(ms_mm, 5), "spmmv_gflops": round(f / ms_mm, 2),
+                              "singles_ms": round(ms_sep, 5), "singles_gflops": round(f / ms_sep, 2),
+                              "singles_graph_ms": round(ms_gr, 5), "singles_graph_gflops": round(f / ms_gr, 2),
+                              "tile": t, "vectors_per_lane": vpl}
+            del g1
+        extra["spmmv_laplacian_128"] = small
         # exhaustive autotuner on this matrix: every catalog configuration, plus x in LDS
         from paper_1112_5588_amd import autotune
         log("autotuner leg")

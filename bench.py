@@ -502,8 +502,32 @@ def main() -> int:
                              "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
                              "tuned_over_plain": round(plain / t_all[best], 3)}
-        result["extra"] = extra
+        # the skewed-row workload: global sort vs sort windows 2^10..2^16 (padding and time),
+        # several lanes per row, and ELLPACK-R's padded size (planned, not allocated)
+        log("power-law leg")
         del M, x_dev, y_dev
+        torch.cuda.empty_cache()
+        P, _ = make_workload("powerlaw", args.dtype)
+        xp = torch.from_numpy(synth.dense_x(P.n_cols, 3)).to("cuda", tdt)
+        yp_ = torch.empty(P.n_rows, dtype=tdt, device="cuda")
+        bp = (vbytes + 4) * P.nnz + 2 * vbytes * P.n_rows
+        pl = {"nnz": P.nnz, "ellpack_r_stored": EllrMatrix.plan(P).nnz_stored}
+        for label, kw in (("global_split512", dict(layout="block", split_len=512)),
+                          ("global_nosplit", dict(layout="block", split_len=-1)),
+                          ("w1024", dict(layout="block", sort_window=1024, split_len=512)),
+                          ("w4096", dict(layout="block", sort_window=4096, split_len=512)),
+                          ("w16384", dict(layout="block", sort_window=16384, split_len=512)),
+                          ("w65536", dict(layout="block", sort_window=65536, split_len=512)),
+                          ("global_lanes4", dict(layout="block", lanes=4))):
+            Mp = PjdsMatrix.from_csr(P, **kw)
+            ms_p = time_launches(lambda: Mp.spmv(xp, yp_, y_permuted=True), 20, 3)
+            pl[label] = {"ms": round(ms_p, 5), "GBps_alg": round(bp / ms_p / 1e6, 1),
+                         "nnz_stored": Mp.info.nnz_stored,
+                         "padding": round(Mp.info.nnz_stored / P.nnz - 1, 4)}
+            del Mp
+        extra["powerlaw"] = pl
+        del P, xp, yp_
+        result["extra"] = extra
         torch.cuda.empty_cache()
         if not args.no_batch:
             result["batch"] = batch_leg(torch)

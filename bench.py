@@ -502,6 +502,22 @@ def main() -> int:
                              "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
                              "tuned_over_plain": round(plain / t_all[best], 3)}
+        # the same matrix with FP32 values (values rounded to nearest), headline configuration
+        if args.dtype == "f64":
+            A32 = A.astype(np.float32)
+            M32 = PjdsMatrix.from_csr(A32, block_height=args.block_height, layout=args.layout,
+                                      sort_window=args.sort_window)
+            x32 = torch.from_numpy(x_np).to("cuda", torch.float32)
+            y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+            if args.x_halo >= 0:
+                ms32 = time_launches(lambda: M32.spmv_xlds(x32, y32, x_halo=args.x_halo, tile_rows=args.tile_rows,
+                                                           y_permuted=True), 100, 10)
+            else:
+                ms32 = time_launches(lambda: M32.spmv(x32, y32, y_permuted=True), 100, 10)
+            b32 = 8 * nnz + 8 * n
+            extra["fp32"] = {"ms": round(ms32, 5), "GBps_alg": round(b32 / ms32 / 1e6, 1),
+                             "gflops": round(2 * nnz / ms32 / 1e6, 2), "alg_bytes": b32}
+            del A32, M32, x32, y32
         # the skewed-row workload: global sort vs sort windows 2^10..2^16 (padding and time),
         # several lanes per row, and ELLPACK-R's padded size (planned, not allocated)
         log("power-law leg")

@@ -41,7 +41,7 @@ extern "C" {
 #define PJDS_ERR_OVERFLOW    (-3)  /* a size or offset exceeds what the format can address   */
 #define PJDS_ERR_NOMEM       (-4)  /* host allocation failed                                 */
 #define PJDS_ERR_HIP         (-5)  /* the HIP runtime reported an error (launch, graph, event) */
-#define PJDS_ERR_UNSUPPORTED (-6)  /* valid request outside what this build implements       */
+#define PJDS_ERR_UNSUPPORTED (-6)  /* valid request outside what the library implements     */
 
 /* ---- value types ------------------------------------------------------------------- */
 #define PJDS_F64 0

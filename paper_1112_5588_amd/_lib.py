@@ -119,8 +119,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                              "or python -m paper_1112_5588_amd.build")
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1112_5588_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)

@@ -544,9 +544,9 @@ def main() -> int:
         extra["powerlaw"] = pl
         del P, xp, yp_
         result["extra"] = extra
+    if not args.no_batch:
         torch.cuda.empty_cache()
-        if not args.no_batch:
-            result["batch"] = batch_leg(torch)
+        result["batch"] = batch_leg(torch)
 
     print(json.dumps(result), flush=True)
     return 0

@@ -391,7 +391,19 @@ def main() -> int:
         from paper_1112_5588_amd import autotune
         log("autotuner leg")
         xo = torch.from_numpy(x_np).to("cuda", tdt)
+        t0_at = time.perf_counter()
         t_cat = autotune.time_all(A, x=xo)
+        exhaustive_s = time.perf_counter() - t0_at
+        # the learned tuner on the same matrix: features on the host, one network inference
+        from paper_1112_5588_amd import tuner as _tn
+        t0_at = time.perf_counter()
+        feats = _lib.pjds_features(A.n_rows, A.n_cols, np.ascontiguousarray(A.row_ptr, np.int64),
+                                   np.ascontiguousarray(A.col, np.int32))
+        model = _tn.Model.load(os.path.join(ROOT, "paper_1112_5588_amd", "tuner_data", "model.json"))
+        pick_i, pick_margin = _tn.predict_matrices(model, np.asarray(feats, np.float64)[None, :],
+                                                   np.array([float(nnz)]))
+        learned_s = time.perf_counter() - t0_at
+        learned_pick = autotune.CONFIG_NAMES[int(pick_i[0])]
         lds = {}
         for sw, halo, tile in ((512, 1024, 512), (1024, 1024, 1024)):   # LDS forms outside the catalog
             Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
@@ -501,7 +513,13 @@ def main() -> int:
         extra["autotune"] = {"ms": {k: round(v, 5) for k, v in t_all.items()}, "best": best,
                              "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
-                             "tuned_over_plain": round(plain / t_all[best], 3)}
+                             "tuned_over_plain": round(plain / t_all[best], 3),
+                             "exhaustive_search_s": round(exhaustive_s, 2),
+                             "learned": {"pick": learned_pick, "margin": round(float(pick_margin[0]), 4),
+                                         "pick_ms": round(t_cat[learned_pick], 5),
+                                         "regret_vs_catalog_best": round(t_cat[learned_pick] / min(t_cat.values()) - 1, 4),
+                                         "over_plain": round(plain / t_cat[learned_pick], 3),
+                                         "tuning_s": round(learned_s, 3)}}
         # the same matrix with FP32 values (values rounded to nearest), headline configuration
         if args.dtype == "f64":
             A32 = A.astype(np.float32)

@@ -479,15 +479,17 @@ def main() -> int:
             "eq4_nnzr_min_tenth_penalty": {"alpha0": round(pmodel.nnzr_bound_tenth_penalty(ratio, 0.0), 1),
                                            "alpha1": round(pmodel.nnzr_bound_tenth_penalty(ratio, 1.0), 1)}}
         del xh, yh, xd2
-        # T lanes per row (block layout, same sort window, x through the caches) on this matrix
+        # T lanes per row (block layout, same sort window, x through the caches) on this matrix,
+        # and the sliced formats the outlook names: rows sorted only inside each 64-row slice
+        # (sliced ELLPACK's padding; with T lanes, sliced ELLR-T's)
         lanes_leg = {}
-        for T in (2, 4, 8):
-            Ml = PjdsMatrix.from_csr(A, layout="block", sort_window=args.sort_window, lanes=T)
+        for T, sw_l in ((2, args.sort_window), (4, args.sort_window), (8, args.sort_window), (1, 64), (4, 64)):
+            Ml = PjdsMatrix.from_csr(A, layout="block", sort_window=sw_l, lanes=T)
             xo = torch.from_numpy(x_np).to("cuda", tdt)
             yl = torch.empty(n, dtype=tdt, device="cuda")
             ms_t = time_launches(lambda: Ml.spmv(xo, yl, y_permuted=True), 50, 5)
-            lanes_leg[f"T{T}"] = {"ms": round(ms_t, 5), "GBps_alg": round(b_alg / ms_t / 1e6, 1),
-                                  "nnz_stored": Ml.info.nnz_stored}
+            lanes_leg[f"T{T}" if sw_l == args.sort_window else f"sliced_w{sw_l}_T{T}"] = {
+                "ms": round(ms_t, 5), "GBps_alg": round(b_alg / ms_t / 1e6, 1), "nnz_stored": Ml.info.nnz_stored}
             del Ml
         extra["lanes_per_row"] = lanes_leg
         # local/non-local split (vector mode with overlap): y written, then read and written again
@@ -552,7 +554,11 @@ def main() -> int:
                           ("w4096", dict(layout="block", sort_window=4096, split_len=512)),
                           ("w16384", dict(layout="block", sort_window=16384, split_len=512)),
                           ("w65536", dict(layout="block", sort_window=65536, split_len=512)),
-                          ("global_lanes4", dict(layout="block", lanes=4))):
+                          ("global_lanes4", dict(layout="block", lanes=4)),
+                          # rows sorted only inside each 64-row slice: the padding of sliced
+                          # ELLPACK, and with 4 lanes per row that of sliced ELLR-T
+                          ("sliced_ellpack_w64", dict(layout="block", sort_window=64, split_len=512)),
+                          ("sliced_ellr_t4_w64", dict(layout="block", sort_window=64, lanes=4))):
             Mp = PjdsMatrix.from_csr(P, **kw)
             ms_p = time_launches(lambda: Mp.spmv(xp, yp_, y_permuted=True), 20, 3)
             pl[label] = {"ms": round(ms_p, 5), "GBps_alg": round(bp / ms_p / 1e6, 1),

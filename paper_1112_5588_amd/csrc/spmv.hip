@@ -242,9 +242,8 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
 }
 
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
-// A workgroup of NT threads (256, 512 or 1024) owns `tile` consecutive sorted rows (a
-// multiple of 256; NT = tile when tile is 512 or 1024, so every row of the tile runs at
-// once).  Sorting never moves a row out of its window of `window` original rows, so the
+// A workgroup of NT threads (256 or 512) owns `tile` consecutive sorted rows (a multiple of
+// 256; NT = 512 when the tile is a multiple of 512, so a 512-row tile runs in one pass).  Sorting never moves a row out of its window of `window` original rows, so the
 // tile's rows are original rows inside [lo_r, hi_r), the union of the windows the tile
 // touches.  The workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into
 // LDS once with coalesced loads, then runs its rows NT at a time; entries whose column falls
@@ -666,8 +665,9 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
     const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), in.n_cols);
     const dim3 grid(unsigned(ceil_div(in.n_pad, tile)));
     const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
-    // a workgroup as wide as the tile when the tile is 512 or 1024 rows, else 256 threads
-    const int nt = tile % 1024 == 0 ? 1024 : tile % 512 == 0 ? 512 : kBlock;
+    // 512 threads when the tile is a multiple of 512 rows, else 256 (1024-thread workgroups
+    // measured slower: longer waits at the barrier, fewer workgroups per CU)
+    const int nt = tile % 512 == 0 ? 512 : kBlock;
     auto go = [&](auto tag) {
         using T = decltype(tag);
         const int br = in.block_height;
@@ -677,8 +677,7 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
                            static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
                            static_cast<T *>(d_y), make_epi<T>(ea), flags)
 #define PJDS_XLDS_CASE(B)                                                                                 \
-        if (nt == 1024) PJDS_XLDS_LAUNCH(B, 1024);                                                         \
-        else if (nt == 512) PJDS_XLDS_LAUNCH(B, 512);                                                      \
+        if (nt == 512) PJDS_XLDS_LAUNCH(B, 512);                                                           \
         else PJDS_XLDS_LAUNCH(B, kBlock)
         if (br == 32) { PJDS_XLDS_CASE(32); }
         else if (br == 64) { PJDS_XLDS_CASE(64); }

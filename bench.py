@@ -157,9 +157,11 @@ def main() -> int:
     ap.add_argument("--split-len", type=int, default=0)
     ap.add_argument("--sort-window", type=int, default=512, help="0 = global sort")
     ap.add_argument("--xcd-remap", action="store_true")
-    ap.add_argument("--x-halo", type=int, default=512,
+    ap.add_argument("--x-halo", type=int, default=768,
                     help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0); -1: x through the caches")
-    ap.add_argument("--tile-rows", type=int, default=512, help="rows per workgroup of the LDS path")
+    ap.add_argument("--tile-rows", type=int, default=1024, help="rows per workgroup of the LDS path")
+    ap.add_argument("--one-row", dest="two_rows", action="store_false",
+                    help="LDS path: one row per lane (default: two adjacent rows per lane, 2-wide loads)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="lanes per row (power of two up to 64, block layout, x through the caches)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -211,7 +213,7 @@ def main() -> int:
     if args.x_halo >= 0:
         def step():
             M.spmv_xlds(x_dev, y_dev, x_halo=args.x_halo, tile_rows=args.tile_rows, y_permuted=y_perm,
-                        xcd_remap=args.xcd_remap)
+                        xcd_remap=args.xcd_remap, two_rows=args.two_rows)
     else:
         def step():
             M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
@@ -242,6 +244,8 @@ def main() -> int:
         out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
 
     lanes_key = f"_T{args.lanes}" if args.lanes > 1 else ""
+    if args.x_halo >= 0 and args.two_rows:
+        lanes_key += "_2rows"
     traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_t{args.tile_rows}_{args.mode}{lanes_key}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",
@@ -261,10 +265,11 @@ def main() -> int:
                    "layout": args.layout, "mode": args.mode, "nnz_stored": M.info.nnz_stored,
                    "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
                    "tile_rows": args.tile_rows if args.x_halo >= 0 else None,
+                   "rows_per_lane": 2 if (args.x_halo >= 0 and args.two_rows) else 1,
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "pjds_spmv_lds_kernel" if args.x_halo >= 0 else
+                     "kernel": ("pjds_spmv_lds2_kernel" if args.two_rows else "pjds_spmv_lds_kernel") if args.x_halo >= 0 else
                                ("pjds_lanes_kernel" if args.lanes > 1 else "pjds_spmv_kernel"),
                      "alg_bytes_per_launch": b_alg},
         "cpu_baseline": cpu,
@@ -423,18 +428,20 @@ def main() -> int:
             bufs = Ms.lanczos_buffers()
             al = torch.empty(steps, dtype=torch.float64, device="cuda")
             be = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
-            ms_l = time_launches(lambda: Ms.lanczos(v0, steps, x_halo=512, tile_rows=512, alpha=al, beta=be,
-                                                    buffers=bufs), 5, 1)
+            ms_l = time_launches(lambda: Ms.lanczos(v0, steps, x_halo=args.x_halo, tile_rows=args.tile_rows,
+                                                    alpha=al, beta=be, buffers=bufs), 5, 1)
             g = torch.cuda.CUDAGraph()
             cs = torch.cuda.Stream()
             cs.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(cs):
                 with torch.cuda.graph(g, stream=cs):
-                    Ms.lanczos(v0, steps, x_halo=512, tile_rows=512, alpha=al, beta=be, buffers=bufs)
+                    Ms.lanczos(v0, steps, x_halo=args.x_halo, tile_rows=args.tile_rows, alpha=al, beta=be,
+                               buffers=bufs)
             torch.cuda.current_stream().wait_stream(cs)
             ms_g = time_launches(g.replay, 5, 1)
             ys = torch.empty(n, dtype=torch.float64, device="cuda")
-            ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=512, tile_rows=512, y_permuted=True), 50, 5)
+            ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=args.x_halo, tile_rows=args.tile_rows,
+                                                      y_permuted=True, two_rows=True), 50, 5)
             extra["lanczos"] = {"steps": steps, "ms_per_step_eager": round(ms_l / steps, 5),
                                 "ms_per_step_graph": round(ms_g / steps, 5), "ms_product_alone": round(ms_p, 5),
                                 "vector_passes_per_step": 6,
@@ -531,7 +538,7 @@ def main() -> int:
             y32 = torch.empty(n, dtype=torch.float32, device="cuda")
             if args.x_halo >= 0:
                 ms32 = time_launches(lambda: M32.spmv_xlds(x32, y32, x_halo=args.x_halo, tile_rows=args.tile_rows,
-                                                           y_permuted=True), 100, 10)
+                                                           y_permuted=True, two_rows=args.two_rows), 100, 10)
             else:
                 ms32 = time_launches(lambda: M32.spmv(x32, y32, y_permuted=True), 100, 10)
             b32 = 8 * nnz + 8 * n

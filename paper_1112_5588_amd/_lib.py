@@ -31,6 +31,7 @@ PJDS_LAYOUT_BLOCK = 0x1
 PJDS_SYMMETRIC = 0x2
 PJDS_Y_PERMUTED = 0x4
 PJDS_XCD_REMAP = 0x8
+PJDS_TWO_ROWS = 0x10
 PJDS_LANES_SHIFT = 8
 PJDS_LANES_MASK = 0x7 << PJDS_LANES_SHIFT
 

@@ -158,7 +158,7 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
         ea.bscale = -1.0;
         if (x_halo >= 0)
             launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, uj, w, x_halo, tile_rows, ea,
-                        PJDS_Y_PERMUTED, s);
+                        PJDS_Y_PERMUTED | PJDS_TWO_ROWS, s);
         else
             launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, uj, w, ea,
                             PJDS_Y_PERMUTED, s);

@@ -186,6 +186,64 @@ __device__ __forceinline__ T row_range_sum(int64_t base, int64_t base_lead, int 
     return acc;
 }
 
+// R adjacent sorted rows per lane (R = kRowsPerLane).  At step j the slots of rows i .. i+R-1
+// (i a multiple of R) are neighbours in both layouts, so a lane reads their values with one
+// R-wide load and their column indices with another: a wave instruction moves R times the
+// bytes of a 1-wide load.  Row i is the lane's longest (rows are sorted), so a lane past row i
+// re-reads lane 0's slots, and padding slots of its shorter rows are read but never added.
+constexpr int kRowsPerLane = 2;
+template <class T, int R>
+struct VecR { typedef T type __attribute__((ext_vector_type(R))); };
+template <int R>
+struct IdxR { typedef int32_t type __attribute__((ext_vector_type(R))); };
+
+template <int U, bool CLAMP, int R, class T, class Addr, class XR>
+__device__ __forceinline__ void row_steps_r(T (&acc)[R], int jb, int j1, const int (&len)[R], int64_t base,
+                                            int64_t base_lead, const Addr &addr, const int32_t *__restrict__ col_p,
+                                            const T *__restrict__ val_p, const XR &xr) {
+    typedef typename VecR<T, R>::type V;
+    typedef typename IdxR<R>::type I;
+    V v[U];
+    I c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = CLAMP ? min(jb + u, j1 - 1) : jb + u;
+        const int64_t a = addr(j, j < len[0] ? base : base_lead);
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(val_p + a));
+        c[u] = __builtin_nontemporal_load(reinterpret_cast<const I *>(col_p + a));
+    }
+    T xv[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) xv[u][q] = xr(c[u][q]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool on = !CLAMP || jb + u < j1;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T s = __builtin_fma(v[u][q], xv[u][q], acc[q]);
+            acc[q] = (on && jb + u < len[q]) ? s : acc[q];
+        }
+    }
+}
+
+// All R rows' sums over steps [0, j1): full groups, then one clamped group.
+template <int R, class T, class Addr, class XR>
+__device__ __forceinline__ void row_group_sum(T (&acc)[R], int64_t base, int64_t base_lead, const int (&len)[R], int j1,
+                                              const Addr &addr, const int32_t *__restrict__ col_p,
+                                              const T *__restrict__ val_p, const XR &xr) {
+    constexpr int U = R >= 4 ? 2 : 4;                // 8 entries in flight per lane
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = T(0);
+    int jb = 0;
+    for (; jb + U <= j1; jb += U) row_steps_r<U, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    const int r = j1 - jb;
+    if (r > 2) row_steps_r<4, true, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r == 2) row_steps_r<2, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+    else if (r == 1) row_steps_r<1, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+}
+
 template <class T, bool JD, int BR>
 __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     int64_t n_rows, int64_t n_pad, int64_t n_groups, int64_t n_chunks, int32_t split_len,
@@ -243,9 +301,9 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
 
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
 // A workgroup of NT threads (256 or 512) owns `tile` consecutive sorted rows (a multiple of
-// 256; NT = 512 when the tile is a multiple of 512, so a 512-row tile runs in one pass).  Sorting never moves a row out of its window of `window` original rows, so the
-// tile's rows are original rows inside [lo_r, hi_r), the union of the windows the tile
-// touches.  The workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into
+// 256; NT = 512 when the tile is a multiple of 512, so a 512-row tile runs in one pass).
+// Sorting never moves a row out of its window of `window` original rows, so the tile's rows
+// are original rows inside [lo_r, hi_r), the union of the windows the tile touches.  The workgroup copies x[lo_r - halo, hi_r + halo) (clipped to the matrix) into
 // LDS once with coalesced loads, then runs its rows NT at a time; entries whose column falls
 // in the staged range read x from LDS, the others from global memory.  Rows are never split
 // here.  Same arithmetic order as pjds_spmv_kernel.
@@ -298,6 +356,68 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
         i = rb + threadIdx.x;
         len = i < n_pad ? row_len[i] : 0;
         base = addr.base(i < n_pad ? i : n_pad - 1);
+    }
+}
+
+// The LDS-staged product with kRowsPerLane adjacent rows per lane (PJDS_TWO_ROWS): NT
+// threads run R NT rows per pass; a wave covers 64 R sorted rows, so the sort window must
+// hold whole groups of that size (their longest row is lane 0's first).  Same staging as
+// above; each row's sum is the same FMAs in the same order as pjds_spmv_kernel.
+template <class T, int BR, int NT>
+__global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
+    int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
+    const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
+    const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+    const int32_t *__restrict__ perm, const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
+    constexpr int R = kRowsPerLane;
+    typedef typename IdxR<R>::type I;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *xs = reinterpret_cast<T *>(lds_raw);
+    const int64_t r0 = int64_t(logical_block(flags)) * tile;
+    const int64_t lo_r = r0 / window * window;
+    const int64_t hi_r = (r0 + tile + window - 1) / window * window;
+    const int64_t lo = lo_r - halo > 0 ? lo_r - halo : 0;
+    const int64_t hi = hi_r + halo < n_cols ? hi_r + halo : n_cols;
+    const PjdsAddr<false, BR> addr{offsets};
+    // n_pad is a multiple of R, so a group never straddles it; groups past it address the
+    // last real group
+    int64_t i = r0 + R * int64_t(threadIdx.x);
+    I lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+    int64_t base = addr.base(i < n_pad ? i : n_pad - R);
+    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
+        T v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int64_t c = c0 + int64_t(u) * NT;
+            v[u] = c < hi ? x[c] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int64_t c = c0 + int64_t(u) * NT;
+            if (c < hi) xs[c - lo] = v[u];
+        }
+    }
+    __syncthreads();
+    const XStaged<T> xr{x, xs, lo, uint32_t(hi > lo ? hi - lo : 0)};
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+    for (int64_t rb = r0;;) {
+        int len[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) len[q] = lv[q];
+        const int m = wave_first(len[0]);
+        T acc[R];
+        row_group_sum<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, xr);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (i + q < n_rows) {
+                const int64_t r = y_perm ? i + q : perm[i + q];
+                epi.store(y, r, acc[q]);
+            }
+        rb += int64_t(R) * NT;
+        if (rb >= r0 + tile || rb >= n_pad) break;
+        i = rb + R * int64_t(threadIdx.x);
+        lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+        base = addr.base(i < n_pad ? i : n_pad - R);
     }
 }
 
@@ -666,11 +786,31 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
     const dim3 grid(unsigned(ceil_div(in.n_pad, tile)));
     const size_t lds = size_t(std::max<int64_t>(cap, 1) * tsize);
     // 512 threads when the tile is a multiple of 512 rows, else 256 (1024-thread workgroups
-    // measured slower: longer waits at the barrier, fewer workgroups per CU)
-    const int nt = tile % 512 == 0 ? 512 : kBlock;
+    // measured slower: longer waits at the barrier, fewer workgroups per CU); with two rows
+    // per lane, half as many threads as rows per tile, at most 512
+    const bool two = flags & PJDS_TWO_ROWS;
+    const int64_t per = two ? tile / kRowsPerLane : tile;     // threads the tile could use
+    const int nt = two ? (per % 512 == 0 ? 512 : per % 256 == 0 ? 256 : 128) : tile % 512 == 0 ? 512 : kBlock;
     auto go = [&](auto tag) {
         using T = decltype(tag);
         const int br = in.block_height;
+        if (two) {
+#define PJDS_XLDS2_LAUNCH(B, N)                                                                           \
+            hipLaunchKernelGGL((pjds_spmv_lds2_kernel<T, B, N>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
+                               in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,              \
+                               static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),          \
+                               static_cast<T *>(d_y), make_epi<T>(ea), flags)
+#define PJDS_XLDS2_CASE(B)                                                                                \
+            if (nt == 512) PJDS_XLDS2_LAUNCH(B, 512);                                                      \
+            else if (nt == 256) PJDS_XLDS2_LAUNCH(B, 256);                                                 \
+            else PJDS_XLDS2_LAUNCH(B, 128)
+            if (br == 32) { PJDS_XLDS2_CASE(32); }
+            else if (br == 64) { PJDS_XLDS2_CASE(64); }
+            else { PJDS_XLDS2_CASE(128); }
+#undef PJDS_XLDS2_CASE
+#undef PJDS_XLDS2_LAUNCH
+            return;
+        }
 #define PJDS_XLDS_LAUNCH(B, N)                                                                            \
         hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B, N>), grid, dim3(N), lds, s, in.n_rows, in.n_cols,     \
                            in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,                  \
@@ -788,7 +928,8 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
                    const void *d_x, void *d_y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
                    void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
-    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP | PJDS_TWO_ROWS))
+        return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
     if (int rc = pjds::check_xlds(*info, dtype, x_halo, tile_rows)) return rc;
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");

@@ -134,11 +134,13 @@ class PjdsMatrix:
 
     def spmv_xlds(self, x: torch.Tensor, y: torch.Tensor | None = None, x_halo: int = 512,
                   tile_rows: int = 0, y_permuted: bool = False, xcd_remap: bool = False,
-                  stream=None) -> torch.Tensor:
-        """y = A x with x staged in LDS per workgroup tile (block layout, sort window % 256 == 0)."""
+                  stream=None, two_rows: bool = False) -> torch.Tensor:
+        """y = A x with x staged in LDS per workgroup tile (block layout, sort window % 256 == 0);
+        two_rows: each lane takes two adjacent rows with 2-wide loads."""
         if y is None:
             y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
         flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
+        flags |= L.PJDS_TWO_ROWS if two_rows else 0
         d = self.d
         L.pjds_spmv_xlds(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], x, y,
                          x_halo, tile_rows, flags, stream)

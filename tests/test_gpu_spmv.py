@@ -320,6 +320,26 @@ def test_xlds_matches_oracle_and_plain_kernel(b_r, window, halo, tile, y_permute
     assert oracle.rel_l2(y, ref) <= 1e-12
     # the same values reach the same FMAs in the same order: bit-identical to the plain kernel
     assert np.array_equal(y, host(M.spmv(xd, y_permuted=y_permuted)))
+    # two adjacent rows per lane: again the same FMAs in the same order
+    assert np.array_equal(y, host(M.spmv_xlds(xd, x_halo=halo, tile_rows=tile, y_permuted=y_permuted,
+                                              two_rows=True)))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n", [300, 1000, 70001])
+def test_xlds_two_rows_ragged_and_fused_update(dtype, n):
+    # row counts that leave a partial tile and a partial 128-row wave; bitwise equal to the
+    # plain kernel in every tile shape
+    A = synth.hh_like(n, seed=24).astype(dtype) if dtype == np.float32 else synth.hh_like(n, seed=24)
+    x = synth.dense_x(A.n_cols, 24)
+    if dtype == np.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=256, keep_host=True)
+    xd = dev(x, M.dtype)
+    for tile in (256, 512, 1024):
+        y = M.spmv_xlds(xd, x_halo=256, tile_rows=tile, two_rows=True)
+        assert oracle.rel_l2(host(y), oracle.csr_spmv(A, x)) <= TOL[M.dtype]
+        assert torch.equal(y, M.spmv(xd))
 
 
 def test_xlds_float32_rectangular_and_wide_rows():

@@ -111,7 +111,80 @@ __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_pe
     if (i < M.n_rows) static_cast<T *>(M.y)[y_perm ? i : M.perm[i]] = acc;
 }
 
+// Two adjacent rows per lane (rows i, i + 1 of wave groups g and g + 1, i even): their slots
+// are neighbours at every step, so one 2-wide load brings both values and one both indices.
+// Row i is the longer, so lane 0's pair serves lanes that are done.  Same FMAs in the same
+// order per row as wave_group.
+template <class T>
+struct Pair2;
+template <>
+struct Pair2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <>
+struct Pair2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+typedef int32_t Int2 __attribute__((ext_vector_type(2)));
+
+template <int U, bool CLAMP, class T, bool JD, int BR>
+__device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, int len1, int64_t base,
+                                       int64_t base_lead, const int64_t *__restrict__ off,
+                                       const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+                                       const T *__restrict__ x) {
+    typedef typename Pair2<T>::type V2;
+    V2 v[U];
+    Int2 c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = CLAMP ? min(jb + u, m - 1) : jb + u;
+        const int64_t b = j < len0 ? base : base_lead;
+        const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(val_p + a));
+        c[u] = __builtin_nontemporal_load(reinterpret_cast<const Int2 *>(col_p + a));
+    }
+    T x0[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        x0[u] = x[c[u].x];
+        x1[u] = x[c[u].y];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool on = !CLAMP || jb + u < m;
+        const T s0 = __builtin_fma(v[u].x, x0[u], a0);
+        const T s1 = __builtin_fma(v[u].y, x1[u], a1);
+        a0 = (on && jb + u < len0) ? s0 : a0;
+        a1 = (on && jb + u < len1) ? s1 : a1;
+    }
+}
+
 template <class T, bool JD, int BR>
+__device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool y_perm) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t i = g * kWave + 2 * lane;
+    const Int2 len = i < M.n_pad ? *reinterpret_cast<const Int2 *>(M.row_len + i) : Int2{0, 0};
+    const int64_t ia = i < M.n_pad ? i : M.n_pad - 2;
+    const int64_t base = JD ? ia : M.offsets[ia / BR] + (ia % BR);
+    const int m = __builtin_amdgcn_readfirstlane(int(len.x));
+    T a0 = T(0), a1 = T(0);
+    if (m > 0) {
+        constexpr int U = 4;
+        const int64_t base_lead = wave_first(base);
+        const T *val_p = static_cast<const T *>(M.val_p);
+        const T *x = static_cast<const T *>(M.x);
+        int jb = 0;
+        for (; jb + U <= m; jb += U)
+            steps2<U, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
+        const int r = m - jb;
+        if (r > 2) steps2<4, true, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
+        else if (r == 2) steps2<2, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
+        else if (r == 1) steps2<1, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
+    }
+    T *y = static_cast<T *>(M.y);
+    if (i < M.n_rows) y[y_perm ? i : M.perm[i]] = a0;
+    if (i + 1 < M.n_rows) y[y_perm ? i + 1 : M.perm[i + 1]] = a1;
+}
+
+// PAIR: each wave takes two wave groups at a time (tiles hold an even number of groups, and
+// every member's sort window holds whole 128-row groups).
+template <class T, bool JD, int BR, bool PAIR>
 __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(const Member *__restrict__ members,
                                                                   const Tile *__restrict__ tiles,
                                                                   int32_t n_tiles, int32_t *counter,
@@ -125,7 +198,10 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(const Member *
         if (t >= n_tiles) return;                  // every wave ends here once the table is drained
         const Tile tile = tiles[t];
         const Member M = members[tile.m];
-        for (int64_t g = tile.g0; g < tile.g1; ++g) wave_group<T, JD, BR>(M, g, y_perm);
+        if (PAIR)
+            for (int64_t g = tile.g0; g < tile.g1; g += 2) wave_group_pair<T, JD, BR>(M, g, y_perm);
+        else
+            for (int64_t g = tile.g0; g < tile.g1; ++g) wave_group<T, JD, BR>(M, g, y_perm);
     }
 }
 
@@ -134,9 +210,11 @@ __global__ void reset_counter_kernel(int32_t *counter) {
 }
 
 template <class T, bool JD, int BR>
-void launch_persistent(int grid, const Member *m, const Tile *t, int32_t nt, int32_t *c, uint32_t f, hipStream_t s) {
+void launch_persistent(int grid, const Member *m, const Tile *t, int32_t nt, int32_t *c, uint32_t f, bool pair,
+                       hipStream_t s) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, c);
-    hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+    if (pair) hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, true>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+    else hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, false>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
 }
 
 }  // namespace
@@ -150,6 +228,7 @@ struct pjds_batch {
     bool jd = true;
     int32_t block_height = 64;
     int grid = 0;
+    bool pair = false;                            // two rows per lane in the persistent kernel
     std::vector<pjds_batch_member> members;       // host copies of the descriptors
     std::vector<pjds_info> infos;
     Member *d_members = nullptr;
@@ -183,13 +262,13 @@ int enqueue(pjds_batch *b, hipStream_t s) {
         auto go = [&](auto tag) {
             using T = decltype(tag);
             if (jd) {
-                if (br == 32) launch_persistent<T, true, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
-                else if (br == 64) launch_persistent<T, true, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
-                else launch_persistent<T, true, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                if (br == 32) launch_persistent<T, true, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                else if (br == 64) launch_persistent<T, true, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                else launch_persistent<T, true, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
             } else {
-                if (br == 32) launch_persistent<T, false, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
-                else if (br == 64) launch_persistent<T, false, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
-                else launch_persistent<T, false, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, s);
+                if (br == 32) launch_persistent<T, false, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                else if (br == 64) launch_persistent<T, false, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                else launch_persistent<T, false, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
             }
         };
         if (b->dtype == PJDS_F64) go(double{});
@@ -256,6 +335,15 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
     for (int32_t k = 0; k < n_members; ++k) b->infos.push_back(*members[k].info);
 
     if (mode == PJDS_BATCH_PERSISTENT) {
+        // two rows per lane when every tile holds an even number of wave groups and every
+        // member is sorted in windows of whole 128-row groups (block layout).  With a global
+        // sort the rows of a wave come from all over the matrix and the doubled gathers per
+        // lane cost more than the wider loads save (measured 7% slower), so it keeps one row.
+        b->pair = groups_per_tile % 2 == 0;
+        for (int32_t k = 0; k < n_members; ++k) {
+            const pjds_info &in = *members[k].info;
+            if (!(in.flags & PJDS_LAYOUT_BLOCK) || in.sort_window >= in.n_rows || in.sort_window % 128) b->pair = false;
+        }
         std::vector<Member> dm(static_cast<size_t>(n_members));
         // Members are visited largest first and each member's tiles stay together, so the
         // waves running at any moment share one member's x in cache; the small members at

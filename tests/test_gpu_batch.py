@@ -91,14 +91,39 @@ def test_graph_replays_are_idempotent(mode):
     B.close()
 
 
-def test_full_size_uneven_batch_sampled():
+@pytest.mark.parametrize("b_r,window,yp", [(64, 256, False), (64, 256, True), (32, 128, True), (128, 512, False)])
+def test_two_rows_per_lane_batch_bitwise(b_r, window, yp):
+    # members sorted in windows of whole 128-row groups and an even tile size: the persistent
+    # kernel takes two rows per lane; it must still equal the single-matrix kernel bit for bit
+    sizes = [600, 1000, 4097, 20000, 513, 777]      # every member longer than its window
+    mats, xs, As = [], [], []
+    for m, n in enumerate(sizes):
+        A = synth.banded_stratified(n, 2000 + m)
+        As.append(A)
+        mats.append(PjdsMatrix.from_csr(A, block_height=b_r, layout="block", sort_window=window, split_len=-1,
+                                        keep_host=True))
+        xs.append(torch.from_numpy(synth.dense_x(n, 2000 + m)).cuda())
+    B, ys = run_batch(mats, xs, L.PJDS_BATCH_PERSISTENT, y_permuted=yp, groups_per_tile=4)
+    for A, M, x, y in zip(As, mats, xs, ys):
+        assert torch.equal(M.spmv(x, y_permuted=yp), y)
+        ref = oracle.csr_spmv(A, x.cpu().numpy())
+        if yp:
+            ref = ref[M.host["perm"]]
+        assert oracle.rel_l2(y.cpu().numpy(), ref) <= 1e-12
+    B.close()
+
+
+@pytest.mark.parametrize("window", [0, 256])
+def test_full_size_uneven_batch_sampled(window):
     # 512 members, rows log-uniform in [1e3, 5e5], 3..60 entries per row: generated on the
-    # GPU by the torch twin of the generator, converted on the host, one persistent launch.
+    # GPU by the torch twin of the generator, converted on the host, one persistent launch;
+    # global sort (one row per lane) and windows of 256 (two rows per lane), as the benchmark
     sizes = synth.uneven_batch_sizes(512)
     mats, xs = [], []
+    kw = dict(layout="block", sort_window=window) if window else {}
     for m, n in enumerate(sizes):
         rp, col, val = torchgen.banded_stratified(int(n), 1000 + m, device="cuda")
-        mats.append(PjdsMatrix.from_arrays(int(n), int(n), rp, col, val, split_len=-1))
+        mats.append(PjdsMatrix.from_arrays(int(n), int(n), rp, col, val, split_len=-1, **kw))
         xs.append(torchgen.dense_x(int(n), 1000 + m, device="cuda"))
         del rp, col, val
     total_nnz = sum(M.info.nnz for M in mats)

@@ -60,9 +60,12 @@ extern "C" {
                                     coalesced; default scatters y to the original row order       */
 #define PJDS_XCD_REMAP     0x8u  /* renumber workgroups so each of the 8 XCDs processes one
                                     contiguous range of row blocks (default: hardware round robin) */
-#define PJDS_TWO_ROWS      0x10u /* pjds_spmv_xlds only: each lane takes two adjacent sorted rows,
-                                    reading both rows' values (and indices) with one 2-wide load;
-                                    same sums, bit for bit (pjds_lanczos's LDS path uses it)      */
+#define PJDS_TWO_ROWS      0x10u /* pjds_spmv and pjds_spmv_xlds: each lane takes two adjacent
+                                    sorted rows, reading both rows' values (and indices) with one
+                                    2-wide load; same sums, bit for bit.  pjds_spmv needs no
+                                    long-row work items (ERR_UNSUPPORTED) and a global sort or a
+                                    window that is a multiple of 128 (ERR_ARG); pjds_lanczos's
+                                    LDS path uses it                                              */
 /* Lanes per row (conversion flag, with PJDS_LAYOUT_BLOCK): PJDS_LANES(k) lets T = 2^k lanes
  * (k = 1..6) share each sorted row, the idea of the sliced ELLR-T format that the outlook of
  * Sect. 4 names beside pJDS.  The block height must then be b_r = 64 / T, so one block fills

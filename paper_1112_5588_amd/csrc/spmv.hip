@@ -299,6 +299,39 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     }
 }
 
+// The plain product with kRowsPerLane adjacent rows per lane (PJDS_TWO_ROWS): one wave per
+// 64 R consecutive sorted rows, x through the caches.  For matrices without long-row work
+// items whose sort holds whole 64 R-row groups (a global sort, or windows that are a multiple
+// of 64 R); same FMAs in the same order per row as pjds_spmv_kernel.
+template <class T, bool JD, int BR>
+__global__ __launch_bounds__(kBlock) void pjds_spmv2_kernel(
+    int64_t n_rows, int64_t n_pad, int64_t n_waves, const int32_t *__restrict__ row_len,
+    const int64_t *__restrict__ offsets, const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
+    const int32_t *__restrict__ perm, const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
+    constexpr int R = kRowsPerLane;
+    typedef typename IdxR<R>::type I;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (w >= n_waves) return;
+    const int64_t i = w * (kWave * R) + int64_t(R) * lane;
+    const I lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+    const PjdsAddr<JD, BR> addr{offsets};
+    const int64_t base = addr.base(i < n_pad ? i : n_pad - R);    // n_pad is a multiple of R
+    int len[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) len[q] = lv[q];
+    const int m = wave_first(len[0]);
+    T acc[R];
+    row_group_sum<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        if (i + q < n_rows) {
+            const int64_t r = y_perm ? i + q : perm[i + q];
+            epi.store(y, r, acc[q]);
+        }
+}
+
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
 // A workgroup of NT threads (256 or 512) owns `tile` consecutive sorted rows (a multiple of
 // 256; NT = 512 when the tile is a multiple of 512, so a 512-row tile runs in one pass).
@@ -647,6 +680,16 @@ void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, con
                        static_cast<T *>(y), make_epi<T>(ea), flags);
 }
 
+template <class T, bool JD, int BR>
+void launch_pjds2(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp, const void *vp,
+                  const int32_t *perm, const void *x, void *y, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
+    const int64_t waves = ceil_div(in.n_pad, int64_t(kWave) * kRowsPerLane);
+    const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)));
+    hipLaunchKernelGGL((pjds_spmv2_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad, waves, rl, off,
+                       cp, static_cast<const T *>(vp), perm, static_cast<const T *>(x), static_cast<T *>(y),
+                       make_epi<T>(ea), flags);
+}
+
 template <class T, bool JD, int BR, int LPR, int VPL>
 void launch_spmmv_lv(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp,
                      const void *vp, const int32_t *perm, int32_t k, const void *X, void *Y,
@@ -727,6 +770,11 @@ struct SpmvK {
     template <class... A>
     static void run(A &&...a) { launch_pjds<T, JD, BR>(a...); }
 };
+template <class T, bool JD, int BR>
+struct Spmv2K {
+    template <class... A>
+    static void run(A &&...a) { launch_pjds2<T, JD, BR>(a...); }
+};
 // The single-vector product for any pJDS matrix: T lanes per row, or one lane per row.
 void launch_product(const pjds_info &in, const int32_t *rl, const int64_t *off, const int32_t *cp, const void *vp,
                     const int32_t *perm, const int32_t *sched, void *work, int32_t dtype, const void *x, void *y,
@@ -736,8 +784,24 @@ void launch_product(const pjds_info &in, const int32_t *rl, const int64_t *off, 
         else launch_lanes<float>(in, rl, off, cp, vp, perm, x, y, ea, flags, s);
         return;
     }
+    if (flags & PJDS_TWO_ROWS) {
+        dispatch<Spmv2K>(dtype, !(in.flags & PJDS_LAYOUT_BLOCK), in.block_height, in, rl, off, cp, vp, perm, x, y, ea,
+                         flags, s);
+        return;
+    }
     dispatch<SpmvK>(dtype, !(in.flags & PJDS_LAYOUT_BLOCK), in.block_height, in, rl, off, cp, vp, perm, sched, work,
                     x, y, ea, flags, s);
+}
+
+// Whether the plain product can take two rows per lane: no long-row work items, one lane per
+// row, and a sort that keeps whole 64 R-row groups sorted.
+int check_two_rows(const pjds_info &in) {
+    if (in.n_chunks) return fail(PJDS_ERR_UNSUPPORTED, "two rows per lane with long-row work items (convert with split_len < 0)");
+    if (lanes_of(in) > 1) return fail(PJDS_ERR_UNSUPPORTED, "two rows per lane with several lanes per row");
+    const int64_t group = int64_t(kWave) * kRowsPerLane;
+    if (in.sort_window < in.n_rows && in.sort_window % group)
+        return fail(PJDS_ERR_ARG, "two rows per lane need a sort window that is a multiple of %lld", (long long)group);
+    return PJDS_OK;
 }
 
 template <class T, bool JD, int BR>
@@ -865,7 +929,10 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               const int32_t *d_sched, void *d_work, int32_t dtype, const void *d_x, void *d_y,
               uint32_t flags, void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
-    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP)) return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP | PJDS_TWO_ROWS))
+        return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & PJDS_TWO_ROWS)
+        if (int rc = check_two_rows(*info)) return rc;
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");

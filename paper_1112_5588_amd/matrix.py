@@ -91,10 +91,11 @@ class PjdsMatrix:
         return self.info.n_cols
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, y_permuted: bool = False,
-             xcd_remap: bool = False, stream=None) -> torch.Tensor:
+             xcd_remap: bool = False, stream=None, two_rows: bool = False) -> torch.Tensor:
         if y is None:
             y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
         flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
+        flags |= L.PJDS_TWO_ROWS if two_rows else 0
         d = self.d
         L.pjds_spmv(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"],
                     d["sched"] if self.info.n_chunks else None, d["work"], x, y, flags, stream)

@@ -361,3 +361,33 @@ def test_xlds_rejects_unsupported_layouts():
         PjdsMatrix.from_csr(A, layout="block", sort_window=1024).spmv_xlds(xd, x_halo=4000)  # > 64 KiB
     with pytest.raises(L.PjdsError):
         PjdsMatrix.from_csr(A, layout="block", sort_window=1024).spmv_xlds(xd, tile_rows=768)  # 768 vs 1024
+
+
+@pytest.mark.parametrize("b_r,layout,window", [(64, "jd", 0), (32, "jd", 0), (128, "block", 0), (64, "block", 128),
+                                               (64, "block", 512), (32, "block", 256)])
+@pytest.mark.parametrize("y_permuted", [False, True])
+def test_plain_two_rows_bitwise(b_r, layout, window, y_permuted):
+    # two adjacent rows per lane: the same FMAs in the same order as one row per lane
+    A = synth.random_csr(9503, 7000, 44, max_len=60)
+    x = dev(synth.dense_x(7000, 44))
+    M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, sort_window=window, split_len=-1)
+    y1 = M.spmv(x, y_permuted=y_permuted)
+    y2 = M.spmv(x, y_permuted=y_permuted, two_rows=True)
+    assert torch.equal(y1, y2)
+    if not y_permuted:
+        assert oracle.rel_l2(host(y2), oracle.csr_spmv(A, host(x))) <= 1e-12
+
+
+def test_plain_two_rows_float32_and_refusals():
+    A = synth.hh_like(30001, seed=45).astype(np.float32)
+    x = synth.dense_x(A.n_cols, 45).astype(np.float32).astype(np.float64)
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=256, split_len=-1)
+    y = host(M.spmv(dev(x, torch.float32), two_rows=True))
+    assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-5
+    P = synth.powerlaw(1 << 14, seed=46, l_max=2000)
+    with pytest.raises(L.PjdsError) as e:                   # long rows split into work items
+        PjdsMatrix.from_csr(P, split_len=64).spmv(dev(synth.dense_x(P.n_cols, 46)), two_rows=True)
+    assert e.value.code == L.PJDS_ERR_UNSUPPORTED
+    with pytest.raises(L.PjdsError) as e:                   # a window of 64 rows
+        PjdsMatrix.from_csr(A, layout="block", sort_window=64, split_len=-1).spmv(dev(x, torch.float32), two_rows=True)
+    assert e.value.code == L.PJDS_ERR_ARG

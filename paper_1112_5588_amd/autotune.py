@@ -34,6 +34,7 @@ class Config:
     variant: int = 1            # CSR lanes per row
     x_halo: int = -1            # >= 0: x staged in LDS (pjds_spmv_xlds) with this halo
     tile_rows: int = 0          # rows per workgroup of the LDS path
+    two_rows: bool = False      # two adjacent rows per lane (PJDS_TWO_ROWS)
 
     def storage_key(self):
         if self.fmt == "pjds":
@@ -61,6 +62,9 @@ CATALOG: tuple[Config, ...] = (
     Config("csr_v16", "csr", variant=16),
     Config("pjds_b64_w256_lds512", "pjds", 64, "block", 256, x_halo=512, tile_rows=512),
     Config("pjds_b64_w512_lds512", "pjds", 64, "block", 512, x_halo=512, tile_rows=512),
+    Config("pjds_b64_w256_nosplit_2r", "pjds", 64, "block", 256, split_len=-1, two_rows=True),
+    Config("pjds_b64_w256_lds768_t1024_2r", "pjds", 64, "block", 256, x_halo=768, tile_rows=1024, two_rows=True),
+    Config("pjds_b64_w512_lds768_t1024_2r", "pjds", 64, "block", 512, x_halo=768, tile_rows=1024, two_rows=True),
 )
 CONFIG_NAMES = tuple(c.name for c in CATALOG)
 DEFAULT = 0
@@ -113,7 +117,13 @@ def _runner(obj, cfg: Config, x, y):
         if not _lds_fits(obj, cfg):
             return None
         return lambda: obj.spmv_xlds(x, y, x_halo=cfg.x_halo, tile_rows=cfg.tile_rows, y_permuted=True,
-                                     xcd_remap=cfg.xcd_remap)
+                                     xcd_remap=cfg.xcd_remap, two_rows=cfg.two_rows)
+    if cfg.fmt == "pjds" and cfg.two_rows:
+        # a global sort, or windows that are whole 128-row groups, and no long-row work items
+        w, n = obj.info.sort_window, obj.info.n_rows
+        if obj.info.n_chunks or (w < n and w % 128):
+            return None
+        return lambda: obj.spmv(x, y, y_permuted=True, xcd_remap=cfg.xcd_remap, two_rows=True)
     if cfg.fmt == "pjds":
         return lambda: obj.spmv(x, y, y_permuted=True, xcd_remap=cfg.xcd_remap)
     if cfg.fmt == "ellr":

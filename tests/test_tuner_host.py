@@ -13,7 +13,7 @@ def test_catalog_default_is_the_papers_format():
     assert c.fmt == "pjds" and c.block_height == 64 and c.layout == "jd" and c.sort_window == 0
     assert len(set(autotune.CONFIG_NAMES)) == len(autotune.CATALOG)
     keys = {c.storage_key() for c in autotune.CATALOG}
-    assert len(keys) <= 11
+    assert len(keys) <= 12
 
 
 def test_training_specs_are_seeded_and_cover_the_range():

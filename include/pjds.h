@@ -197,7 +197,9 @@ int pjds_spmv_axpby(const pjds_info *info, const int32_t *d_row_len, const int64
  * and the others from global memory.  For matrices whose non-zeros cluster near the diagonal
  * this replaces most scattered global gathers with LDS reads (the right-hand-side reuse that
  * eq. (1) calls alpha).  The staged range, (max(tile_rows, window) + 2*x_halo) values, must
- * fit 64 KiB; ERR_ARG otherwise.  Rows are not split (no schedule or workspace).
+ * fit 64 KiB; ERR_ARG otherwise.  Rows are not split (no schedule or workspace).  Tiles go
+ * to the 8 XCDs in runs of 16 consecutive tiles, so neighbours that share halo values share
+ * an L2; PJDS_XCD_REMAP gives each XCD one contiguous range instead.
  */
 int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                    const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm, int32_t dtype,

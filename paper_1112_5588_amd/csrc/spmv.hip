@@ -53,6 +53,23 @@ __device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
     return (flags & PJDS_XCD_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
 }
 
+// Tiles of the LDS product are handed out in runs of kXcdGroup consecutive tiles per XCD:
+// neighbouring tiles, whose staged x ranges overlap by the halo, then share one L2, while all
+// eight XCDs still stream nearby parts of the matrix (whole contiguous ranges per XCD spread
+// the streams too far apart).  The blocks of an incomplete last round keep their own number.
+// A bijection on [0, grid).
+constexpr uint32_t kXcdGroup = 16;
+
+__device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t grid) {
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    if (k / kXcdGroup >= grid / (kXcds * kXcdGroup)) return b;
+    return (k / kXcdGroup) * (kXcds * kXcdGroup) + x * kXcdGroup + k % kXcdGroup;
+}
+
+__device__ __forceinline__ uint32_t tile_block(uint32_t flags) {
+    return (flags & PJDS_XCD_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : xcd_group(blockIdx.x, gridDim.x);
+}
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
@@ -348,7 +365,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
     const int32_t *__restrict__ perm, const T *__restrict__ x, T *y, Epilogue<T> epi, uint32_t flags) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
-    const int64_t r0 = int64_t(logical_block(flags)) * tile;         // first sorted row of the tile
+    const int64_t r0 = int64_t(tile_block(flags)) * tile;            // first sorted row of the tile
     const int64_t lo_r = r0 / window * window;
     const int64_t hi_r = (r0 + tile + window - 1) / window * window;
     const int64_t lo = lo_r - halo > 0 ? lo_r - halo : 0;
@@ -406,7 +423,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
     typedef typename IdxR<R>::type I;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
-    const int64_t r0 = int64_t(logical_block(flags)) * tile;
+    const int64_t r0 = int64_t(tile_block(flags)) * tile;
     const int64_t lo_r = r0 / window * window;
     const int64_t hi_r = (r0 + tile + window - 1) / window * window;
     const int64_t lo = lo_r - halo > 0 ? lo_r - halo : 0;

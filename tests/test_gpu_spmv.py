@@ -268,16 +268,17 @@ def test_hh_like_full_size_sampled(hh_full, dtype):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_headline_configuration_full_size(hh_full, dtype):
-    # the benchmark's own launch: block layout, sort window 512, x staged in LDS with halo 512
-    # and 512-row tiles, y in the permuted basis; sampled rows against the oracle, the whole
-    # vector bitwise against the plain kernel, and run-to-run reproducibility
+    # the benchmark's own launch: block layout, sort window 256, x staged in LDS with halo 768
+    # and 1024-row tiles (4096 tiles, all in whole XCD groups), two rows per lane, y in the
+    # permuted basis; sampled rows against the oracle, the whole vector bitwise against the
+    # plain kernel and the one-row LDS form, and run-to-run reproducibility
     A = hh_full.astype(dtype) if dtype == np.float32 else hh_full
     x = synth.dense_x(A.n_cols, 1)
     if dtype == np.float32:
         x = x.astype(np.float32).astype(np.float64)
-    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=512, keep_host=True)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=256, keep_host=True)
     xd = dev(x, M.dtype)
-    yd = M.spmv_xlds(xd, x_halo=512, tile_rows=512, y_permuted=True)
+    yd = M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True)
     y = host(yd)
     rows = np.unique(np.concatenate([np.arange(512), np.arange(A.n_rows - 512, A.n_rows),
                                      (synth.uniform01(81, 1, 4096) * A.n_rows).astype(np.int64)]))
@@ -286,6 +287,7 @@ def test_headline_configuration_full_size(hh_full, dtype):
     assert oracle.rel_l2(y[inv[rows]], oracle.csr_spmv(sampled_rows(A, rows), x)) <= TOL[M.dtype]
     assert torch.equal(yd, M.spmv(xd, y_permuted=True))
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=512, tile_rows=512, y_permuted=True))
+    assert torch.equal(yd, M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True))
 
 
 def test_powerlaw_full_size_sampled():

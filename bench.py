@@ -105,9 +105,10 @@ def cpu_baseline(A, x, budget_s: float = 12.0):
 
 def batch_leg(torch) -> dict:
     """512 uneven matrices (rows log-uniform in [1e3, 5e5], 3..60 entries per row, columns
-    within +-4096 of the diagonal), FP64: one persistent launch in a HIP graph vs one launch
-    per member captured in a graph vs one launch per member issued directly; members stored
-    with a global sort (JD layout) and with a 256-row sort window (block layout)."""
+    within +-4096 of the diagonal), FP64: one persistent launch in a HIP graph (x through the
+    caches, or staged in LDS per tile with a 4096-value halo) vs one launch per member captured
+    in a graph vs one launch per member issued directly; members stored with a global sort (JD
+    layout) and with a 256-row sort window (block layout)."""
     import synth
     from synth import torchgen
     from paper_1112_5588_amd import PjdsBatch, PjdsMatrix, _lib
@@ -130,9 +131,11 @@ def batch_leg(torch) -> dict:
         b_alg = 12 * nnz + 16 * rows
         res = {"setup_s": round(t_setup, 1), "nnz_stored": sum(M.info.nnz_stored for M in mats)}
         out["rows"], out["nnz"] = rows, nnz
-        for name, mode in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT), ("per_member_graph", _lib.PJDS_BATCH_GRAPH),
-                           ("direct_launches", _lib.PJDS_BATCH_DIRECT)):
-            B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True)
+        for name, mode, halo in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT, None),
+                                 ("persistent_graph_x_in_lds", _lib.PJDS_BATCH_PERSISTENT, 4096),
+                                 ("per_member_graph", _lib.PJDS_BATCH_GRAPH, None),
+                                 ("direct_launches", _lib.PJDS_BATCH_DIRECT, None)):
+            B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True, x_halo=halo)
             ms = time_launches(B.launch, 10, 2)
             res[name] = {"ms": round(ms, 4), "gflops": round(2 * nnz / ms / 1e6, 1), "GBps_alg": round(b_alg / ms / 1e6, 1)}
             if mode == _lib.PJDS_BATCH_PERSISTENT:

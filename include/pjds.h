@@ -282,6 +282,21 @@ typedef struct pjds_batch pjds_batch;
 /* flags: 0 or PJDS_Y_PERMUTED.  Errors: ERR_ARG (inconsistent members), ERR_HIP, ERR_NOMEM. */
 int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
                       uint32_t flags, int32_t mode, int32_t groups_per_tile, pjds_batch **out);
+/*
+ * A persistent batch (as PJDS_BATCH_PERSISTENT) whose kernel stages x in LDS, the idea of
+ * pjds_spmv_xlds applied per tile: 512-thread workgroups pull tiles of `groups_per_tile` wave
+ * groups (<= 0 -> 16, i.e. 1024 rows); a workgroup copies x[lo, hi) of its member into LDS,
+ * where [lo, hi) are the original rows of the sort windows its sorted rows lie in (the whole
+ * member for a global sort) widened by `x_halo` (>= 0) on each side and clipped to the
+ * member's columns, then its waves pull the tile's wave groups and read x from LDS wherever
+ * the column falls in the staged range, from global memory elsewhere.  The staged range is
+ * cut at 78 KiB (two workgroups per CU on gfx950's 160 KB of LDS); columns past the cut are
+ * read from global memory, so any halo gives the same results, bit for bit those of
+ * PJDS_BATCH_PERSISTENT and pjds_spmv.  Suits members sorted in windows whose non-zeros lie
+ * within about x_halo of the diagonal.  Errors: as pjds_batch_create; ERR_ARG for x_halo < 0.
+ */
+int pjds_batch_create_xlds(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
+                           uint32_t flags, int32_t groups_per_tile, int32_t x_halo, pjds_batch **out);
 /* Enqueue one evaluation of the whole batch on `stream` (asynchronous). */
 int pjds_batch_launch(pjds_batch *batch, void *stream);
 /* Tile count and persistent grid size (workgroups) of a handle; either pointer may be NULL. */

@@ -105,6 +105,7 @@ _SIGS = {
     "mlp_adam_step": [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp],
     "mlp_infer": [_vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "pjds_batch_create": [_i32, ctypes.POINTER(pjds_batch_member), _i32, _u32, _i32, _i32, ctypes.POINTER(_vp)],
+    "pjds_batch_create_xlds": [_i32, ctypes.POINTER(pjds_batch_member), _i32, _u32, _i32, _i32, ctypes.POINTER(_vp)],
     "pjds_batch_launch": [_vp, _vp],
     "pjds_batch_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "pjds_batch_destroy": [_vp],
@@ -279,6 +280,19 @@ def pjds_batch_create(members: list, dtype, flags: int = 0, mode: int = PJDS_BAT
     h = _vp()
     _check(lib().pjds_batch_create(len(members), arr, _dtype_code(dtype), flags, mode,
                                    groups_per_tile, ctypes.byref(h)), "pjds_batch_create")
+    return h.value
+
+
+def pjds_batch_create_xlds(members: list, dtype, flags: int = 0, groups_per_tile: int = 0,
+                           x_halo: int = 4096) -> int:
+    """Like pjds_batch_create (persistent mode) with x staged in LDS per tile."""
+    arr = (pjds_batch_member * len(members))()
+    for k, (info, rl, off, cp, vp, perm, x, y) in enumerate(members):
+        arr[k] = pjds_batch_member(ctypes.pointer(info), _dev(rl), _dev(off), _dev(cp), _dev(vp),
+                                   _dev(perm), _dev(x), _dev(y))
+    h = _vp()
+    _check(lib().pjds_batch_create_xlds(len(members), arr, _dtype_code(dtype), flags, groups_per_tile,
+                                        x_halo, ctypes.byref(h)), "pjds_batch_create_xlds")
     return h.value
 
 

@@ -7,6 +7,10 @@
 //    next tile from one device counter until the table is exhausted (every wave then exits).  A small
 //    fill kernel resets the counter in front of it.  Both kernels are captured once in a
 //    HIP graph; a launch replays it.
+//  * pjds_batch_create_xlds: the persistent kernel with x staged in LDS.  Workgroups (not
+//    waves) pull the tiles; a workgroup copies the x range its tile's sort windows cover, plus
+//    a halo on each side, into LDS, then its waves pull the tile's wave groups from an LDS
+//    counter and read x from LDS wherever the column falls in the staged range.
 //  * PJDS_BATCH_GRAPH: one pjds_spmv launch per member, captured in a HIP graph.
 //  * PJDS_BATCH_DIRECT: one pjds_spmv launch per member, issued on the stream each time.
 // Rows are never split here (no long-row workspace); results equal pjds_spmv's bit for bit
@@ -25,7 +29,6 @@ namespace pjds {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
 #ifndef PJDS_UNROLL
 #define PJDS_UNROLL 8
 #endif
@@ -41,6 +44,8 @@ struct Member {                    // device-side descriptor of one batch member
     const void *x;
     void *y;
     int64_t n_rows, n_pad;
+    int64_t n_cols;
+    int64_t window;                // sort window in rows (n_pad for a global sort)
 };
 
 struct Tile {                      // wave groups [g0, g1) of member m
@@ -59,12 +64,31 @@ __device__ __forceinline__ int64_t wave_first(int64_t v) {
 template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
+// x gathered from global memory
+template <class T>
+struct XGlobal {
+    const T *x;
+    __device__ __forceinline__ T operator()(int32_t c) const { return x[c]; }
+};
+
+// x[lo, lo + n) staged in LDS; columns outside that range read global memory
+template <class T>
+struct XStaged {
+    const T *lds;
+    const T *x;
+    uint32_t lo, n;
+    __device__ __forceinline__ T operator()(int32_t c) const {
+        const uint32_t d = uint32_t(c) - lo;
+        return d < n ? lds[d] : x[c];
+    }
+};
+
 // U entries from jb; with CLAMP, steps at or past m re-read step m - 1 and are masked (one
 // round trip for a ragged tail, no load past the longest row).
-template <int U, bool CLAMP, class T, bool JD, int BR>
+template <int U, bool CLAMP, class T, bool JD, int BR, class XA>
 __device__ __forceinline__ void steps(T &acc, int jb, int m, int len, int64_t base, int64_t base_lead,
                                       const int64_t *__restrict__ off, const int32_t *__restrict__ col_p,
-                                      const T *__restrict__ val_p, const T *__restrict__ x) {
+                                      const T *__restrict__ val_p, const XA &x) {
     T v[U];
     int32_t c[U];
 #pragma unroll
@@ -77,7 +101,7 @@ __device__ __forceinline__ void steps(T &acc, int jb, int m, int len, int64_t ba
     }
     T xv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+    for (int u = 0; u < U; ++u) xv[u] = x(c[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const T s = __builtin_fma(v[u], xv[u], acc);
@@ -87,8 +111,8 @@ __device__ __forceinline__ void steps(T &acc, int jb, int m, int len, int64_t ba
 
 // One wave group of one member: Listing 2 over 64 sorted rows, same arithmetic order as
 // pjds_spmv (entries in stored order, one FMA each).
-template <class T, bool JD, int BR>
-__device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_perm) {
+template <class T, bool JD, int BR, class XA>
+__device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_perm, const XA &x) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + lane;
     const int len = i < M.n_pad ? M.row_len[i] : 0;
@@ -98,7 +122,6 @@ __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_pe
     if (m > 0) {
         const int64_t base_lead = wave_first(base);
         const T *val_p = static_cast<const T *>(M.val_p);
-        const T *x = static_cast<const T *>(M.x);
         int jb = 0;
         for (; jb + kUnroll <= m; jb += kUnroll)
             steps<kUnroll, false, T, JD, BR>(acc, jb, m, len, base, base_lead, M.offsets, M.col_p, val_p, x);
@@ -123,11 +146,11 @@ template <>
 struct Pair2<float> { typedef float type __attribute__((ext_vector_type(2))); };
 typedef int32_t Int2 __attribute__((ext_vector_type(2)));
 
-template <int U, bool CLAMP, class T, bool JD, int BR>
+template <int U, bool CLAMP, class T, bool JD, int BR, class XA>
 __device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, int len1, int64_t base,
                                        int64_t base_lead, const int64_t *__restrict__ off,
                                        const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
-                                       const T *__restrict__ x) {
+                                       const XA &x) {
     typedef typename Pair2<T>::type V2;
     V2 v[U];
     Int2 c[U];
@@ -142,8 +165,8 @@ __device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, in
     T x0[U], x1[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        x0[u] = x[c[u].x];
-        x1[u] = x[c[u].y];
+        x0[u] = x(c[u].x);
+        x1[u] = x(c[u].y);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -155,8 +178,8 @@ __device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, in
     }
 }
 
-template <class T, bool JD, int BR>
-__device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool y_perm) {
+template <class T, bool JD, int BR, class XA>
+__device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool y_perm, const XA &x) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + 2 * lane;
     const Int2 len = i < M.n_pad ? *reinterpret_cast<const Int2 *>(M.row_len + i) : Int2{0, 0};
@@ -168,7 +191,6 @@ __device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool
         constexpr int U = 4;
         const int64_t base_lead = wave_first(base);
         const T *val_p = static_cast<const T *>(M.val_p);
-        const T *x = static_cast<const T *>(M.x);
         int jb = 0;
         for (; jb + U <= m; jb += U)
             steps2<U, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
@@ -198,10 +220,76 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(const Member *
         if (t >= n_tiles) return;                  // every wave ends here once the table is drained
         const Tile tile = tiles[t];
         const Member M = members[tile.m];
+        const XGlobal<T> xa{static_cast<const T *>(M.x)};
         if (PAIR)
-            for (int64_t g = tile.g0; g < tile.g1; g += 2) wave_group_pair<T, JD, BR>(M, g, y_perm);
+            for (int64_t g = tile.g0; g < tile.g1; g += 2) wave_group_pair<T, JD, BR>(M, g, y_perm, xa);
         else
-            for (int64_t g = tile.g0; g < tile.g1; ++g) wave_group<T, JD, BR>(M, g, y_perm);
+            for (int64_t g = tile.g0; g < tile.g1; ++g) wave_group<T, JD, BR>(M, g, y_perm, xa);
+    }
+}
+
+constexpr int kXldsThreads = 512;        // threads of a workgroup of the LDS-staged batch
+constexpr int kXldsStage = 8;            // x values in flight per thread while staging
+constexpr int64_t kXldsMaxBytes = 78 * 1024;   // staged x per workgroup: two workgroups fit a CU
+
+// x staged in LDS: each workgroup pulls a tile, copies x[lo, lo + n) -- the original rows of
+// the sort windows its sorted rows lie in, widened by `halo` on both sides, clipped to the
+// member's columns and to `cap` values -- into LDS, and its waves then pull the tile's wave
+// groups (pairs with PAIR) from a counter in LDS.  The same FMAs in the same order as
+// batch_persistent_kernel; only where x is read from differs.
+template <class T, bool JD, int BR, bool PAIR>
+__global__ __launch_bounds__(kXldsThreads) void batch_xlds_kernel(const Member *__restrict__ members,
+                                                                  const Tile *__restrict__ tiles,
+                                                                  int32_t n_tiles, int32_t *counter,
+                                                                  int32_t cap, int32_t halo, uint32_t flags) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *xs = reinterpret_cast<T *>(lds_raw);
+    __shared__ int32_t s_tile, s_next;
+    const bool y_perm = flags & PJDS_Y_PERMUTED;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_tile = atomicAdd(counter, 1);
+            s_next = 0;
+        }
+        __syncthreads();
+        const int32_t t = s_tile;
+        if (t >= n_tiles) return;                  // the same in every thread: the workgroup leaves together
+        const Tile tile = tiles[t];
+        const Member M = members[tile.m];
+        const T *x = static_cast<const T *>(M.x);
+        const int64_t r0 = int64_t(tile.g0) * kWave;
+        const int64_t r1 = min(int64_t(tile.g1) * kWave, M.n_pad);
+        const int64_t lo_r = r0 / M.window * M.window;
+        const int64_t hi_r = (r1 + M.window - 1) / M.window * M.window;
+        const int64_t lo = max(lo_r - int64_t(halo), int64_t(0));
+        const int64_t hi = min(hi_r + int64_t(halo), M.n_cols);
+        const int32_t n = int32_t(max(min(hi - lo, int64_t(cap)), int64_t(0)));
+        for (int32_t k0 = 0; k0 < n; k0 += kXldsThreads * kXldsStage) {
+            T v[kXldsStage];
+#pragma unroll
+            for (int u = 0; u < kXldsStage; ++u) {
+                const int32_t k = k0 + u * kXldsThreads + int32_t(threadIdx.x);
+                v[u] = k < n ? x[lo + k] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kXldsStage; ++u) {
+                const int32_t k = k0 + u * kXldsThreads + int32_t(threadIdx.x);
+                if (k < n) xs[k] = v[u];
+            }
+        }
+        __syncthreads();
+        const XStaged<T> xa{xs, x, uint32_t(lo), uint32_t(n)};
+        for (;;) {
+            int32_t u = 0;
+            if (lane == 0) u = atomicAdd(&s_next, PAIR ? 2 : 1);
+            u = __shfl(u, 0);
+            const int64_t g = int64_t(tile.g0) + u;
+            if (g >= tile.g1) break;
+            if (PAIR) wave_group_pair<T, JD, BR>(M, g, y_perm, xa);
+            else wave_group<T, JD, BR>(M, g, y_perm, xa);
+        }
+        __syncthreads();                           // LDS and s_tile are reused by the next tile
     }
 }
 
@@ -209,12 +297,28 @@ __global__ void reset_counter_kernel(int32_t *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
+// Persistent launch: `cap` > 0 selects the LDS-staged kernel with that many staged values.
 template <class T, bool JD, int BR>
 void launch_persistent(int grid, const Member *m, const Tile *t, int32_t nt, int32_t *c, uint32_t f, bool pair,
-                       hipStream_t s) {
+                       int32_t cap, int32_t halo, hipStream_t s) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, c);
-    if (pair) hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, true>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
-    else hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, false>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+    const size_t lds = size_t(cap) * sizeof(T);
+    if (cap > 0 && pair)
+        hipLaunchKernelGGL((batch_xlds_kernel<T, JD, BR, true>), dim3(grid), dim3(kXldsThreads), lds, s, m, t, nt, c, cap, halo, f);
+    else if (cap > 0)
+        hipLaunchKernelGGL((batch_xlds_kernel<T, JD, BR, false>), dim3(grid), dim3(kXldsThreads), lds, s, m, t, nt, c, cap, halo, f);
+    else if (pair)
+        hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, true>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+    else
+        hipLaunchKernelGGL((batch_persistent_kernel<T, JD, BR, false>), dim3(grid), dim3(kBlock), 0, s, m, t, nt, c, f);
+}
+
+// Allow the LDS-staged kernel its dynamic LDS beyond the default limit (gfx950 has 160 KB per CU).
+template <class T, bool JD, int BR>
+hipError_t allow_lds(size_t bytes, bool pair) {
+    const void *k = pair ? reinterpret_cast<const void *>(&batch_xlds_kernel<T, JD, BR, true>)
+                         : reinterpret_cast<const void *>(&batch_xlds_kernel<T, JD, BR, false>);
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 }  // namespace
@@ -229,6 +333,8 @@ struct pjds_batch {
     int32_t block_height = 64;
     int grid = 0;
     bool pair = false;                            // two rows per lane in the persistent kernel
+    int32_t cap = 0;                              // > 0: x staged in LDS, this many values per workgroup
+    int32_t halo = 0;
     std::vector<pjds_batch_member> members;       // host copies of the descriptors
     std::vector<pjds_info> infos;
     Member *d_members = nullptr;
@@ -262,13 +368,13 @@ int enqueue(pjds_batch *b, hipStream_t s) {
         auto go = [&](auto tag) {
             using T = decltype(tag);
             if (jd) {
-                if (br == 32) launch_persistent<T, true, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
-                else if (br == 64) launch_persistent<T, true, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
-                else launch_persistent<T, true, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                if (br == 32) launch_persistent<T, true, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
+                else if (br == 64) launch_persistent<T, true, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
+                else launch_persistent<T, true, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
             } else {
-                if (br == 32) launch_persistent<T, false, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
-                else if (br == 64) launch_persistent<T, false, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
-                else launch_persistent<T, false, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, s);
+                if (br == 32) launch_persistent<T, false, 32>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
+                else if (br == 64) launch_persistent<T, false, 64>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
+                else launch_persistent<T, false, 128>(b->grid, b->d_members, b->d_tiles, b->n_tiles, b->d_counter, b->flags, b->pair, b->cap, b->halo, s);
             }
         };
         if (b->dtype == PJDS_F64) go(double{});
@@ -290,10 +396,17 @@ int enqueue(pjds_batch *b, hipStream_t s) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
-                      uint32_t flags, int32_t mode, int32_t groups_per_tile, pjds_batch **out) {
+// Sort window of a member in rows, as the staged kernel uses it: n_pad for a global sort.
+int64_t member_window(const pjds_info &in) {
+    const int64_t w = (in.flags & PJDS_LAYOUT_BLOCK) && in.sort_window < in.n_rows ? in.sort_window : in.n_pad;
+    return std::max<int64_t>(w, 1);
+}
+
+// x_halo < 0: the persistent kernel gathers x through the caches; >= 0: the LDS-staged one.
+int create(int32_t n_members, const pjds_batch_member *members, int32_t dtype, uint32_t flags, int32_t mode,
+           int32_t groups_per_tile, int32_t x_halo, pjds_batch **out) {
     if (!out) return fail(PJDS_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (n_members < 1 || !members) return fail(PJDS_ERR_ARG, "empty batch");
@@ -301,7 +414,8 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
     if (flags & ~PJDS_Y_PERMUTED) return fail(PJDS_ERR_ARG, "unsupported batch flags 0x%x", flags);
     if (mode != PJDS_BATCH_PERSISTENT && mode != PJDS_BATCH_GRAPH && mode != PJDS_BATCH_DIRECT)
         return fail(PJDS_ERR_ARG, "mode %d", mode);
-    if (groups_per_tile <= 0) groups_per_tile = 8;
+    const bool staged = x_halo >= 0;
+    if (groups_per_tile <= 0) groups_per_tile = staged ? 16 : 8;
     const pjds_info &first = *members[0].info;
     for (int32_t k = 0; k < n_members; ++k) {
         const pjds_batch_member &m = members[k];
@@ -357,12 +471,24 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
         for (int32_t k = 0; k < n_members; ++k) {
             const pjds_batch_member &m = members[k];
             const pjds_info &in = *m.info;
-            dm[size_t(k)] = Member{m.d_row_len, m.d_offsets, m.d_col_p, m.d_val_p, m.d_perm, m.d_x, m.d_y, in.n_rows, in.n_pad};
+            dm[size_t(k)] = Member{m.d_row_len, m.d_offsets, m.d_col_p, m.d_val_p, m.d_perm, m.d_x, m.d_y,
+                                   in.n_rows, in.n_pad, in.n_cols, member_window(in)};
         }
+        // the largest x range a tile of the staged kernel needs (the kernel's own formula)
+        const int64_t esz = dtype == PJDS_F64 ? 8 : 4;
+        int64_t need = 0;
         for (int32_t k : order) {
-            const int64_t groups = ceil_div(members[k].info->n_pad, kWave);
-            for (int64_t g = 0; g < groups; g += groups_per_tile)
-                sorted.push_back(Tile{k, int32_t(g), int32_t(std::min(groups, g + groups_per_tile)), 0});
+            const pjds_info &in = *members[k].info;
+            const int64_t groups = ceil_div(in.n_pad, kWave), w = member_window(in);
+            for (int64_t g = 0; g < groups; g += groups_per_tile) {
+                const int64_t g1 = std::min(groups, g + groups_per_tile);
+                sorted.push_back(Tile{k, int32_t(g), int32_t(g1), 0});
+                if (staged) {
+                    const int64_t lo = std::max<int64_t>(g * kWave / w * w - x_halo, 0);
+                    const int64_t hi = std::min<int64_t>(ceil_div(std::min(g1 * kWave, in.n_pad), w) * w + x_halo, in.n_cols);
+                    need = std::max(need, hi - lo);
+                }
+            }
         }
         if (sorted.size() > size_t(INT32_MAX)) { release(b); return fail(PJDS_ERR_OVERFLOW, "too many tiles"); }
         b->n_tiles = int32_t(sorted.size());
@@ -370,7 +496,28 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) { release(b); return hip_fail(e, "device query"); }
-        b->grid = std::max(1, cus) * 8;            // 8 workgroups (32 waves) per CU
+        if (staged) {
+            // wider ranges are cut at the cap (their far ends are read from global memory)
+            b->cap = int32_t(std::max<int64_t>(std::min(need, kXldsMaxBytes / esz), 1));
+            b->halo = x_halo;
+            const int64_t bytes = int64_t(b->cap) * esz;
+            const int per_cu = int(std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (bytes + 1024))));
+            b->grid = std::max(1, cus) * per_cu;
+            auto allow = [&](auto tag) -> hipError_t {
+                using T = decltype(tag);
+                const int br = b->block_height;
+                if (b->jd) return br == 32 ? allow_lds<T, true, 32>(size_t(bytes), b->pair)
+                                 : br == 64 ? allow_lds<T, true, 64>(size_t(bytes), b->pair)
+                                            : allow_lds<T, true, 128>(size_t(bytes), b->pair);
+                return br == 32 ? allow_lds<T, false, 32>(size_t(bytes), b->pair)
+                     : br == 64 ? allow_lds<T, false, 64>(size_t(bytes), b->pair)
+                                : allow_lds<T, false, 128>(size_t(bytes), b->pair);
+            };
+            e = dtype == PJDS_F64 ? allow(double{}) : allow(float{});
+            if (e != hipSuccess) { release(b); return hip_fail(e, "LDS size of the staged batch kernel"); }
+        } else {
+            b->grid = std::max(1, cus) * 8;        // 8 workgroups (32 waves) per CU
+        }
         e = hipMalloc(&b->d_members, sizeof(Member) * dm.size());
         if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(Tile) * std::max<size_t>(sorted.size(), 1));
         if (e == hipSuccess) e = hipMalloc(&b->d_counter, 256);
@@ -398,6 +545,24 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
     }
     *out = b;
     return PJDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
+                      uint32_t flags, int32_t mode, int32_t groups_per_tile, pjds_batch **out) {
+    return create(n_members, members, dtype, flags, mode, groups_per_tile, -1, out);
+}
+
+int pjds_batch_create_xlds(int32_t n_members, const pjds_batch_member *members, int32_t dtype,
+                           uint32_t flags, int32_t groups_per_tile, int32_t x_halo, pjds_batch **out) {
+    if (x_halo < 0) {
+        if (out) *out = nullptr;
+        return fail(PJDS_ERR_ARG, "x_halo %d", x_halo);
+    }
+    return create(n_members, members, dtype, flags, PJDS_BATCH_PERSISTENT, groups_per_tile, x_halo, out);
 }
 
 int pjds_batch_launch(pjds_batch *b, void *stream) {

@@ -241,12 +241,18 @@ class PjdsBatch:
     """
 
     def __init__(self, mats, xs, ys, mode: int = L.PJDS_BATCH_PERSISTENT, y_permuted: bool = False,
-                 groups_per_tile: int = 0):
+                 groups_per_tile: int = 0, x_halo: int | None = None):
+        """``x_halo`` (persistent mode only) stages x in LDS per tile (pjds_batch_create_xlds)."""
         self.mats, self.xs, self.ys = list(mats), list(xs), list(ys)
         members = [(M.info, M.d["row_len"], M.d["offsets"], M.d["col_p"], M.d["val_p"], M.d["perm"], x, y)
                    for M, x, y in zip(self.mats, self.xs, self.ys)]
-        self.handle = L.pjds_batch_create(members, self.mats[0].dtype,
-                                          L.PJDS_Y_PERMUTED if y_permuted else 0, mode, groups_per_tile)
+        flags = L.PJDS_Y_PERMUTED if y_permuted else 0
+        if x_halo is not None:
+            if mode != L.PJDS_BATCH_PERSISTENT:
+                raise ValueError("x_halo needs the persistent mode")
+            self.handle = L.pjds_batch_create_xlds(members, self.mats[0].dtype, flags, groups_per_tile, x_halo)
+        else:
+            self.handle = L.pjds_batch_create(members, self.mats[0].dtype, flags, mode, groups_per_tile)
 
     def launch(self, stream=None) -> None:
         L.pjds_batch_launch(self.handle, stream)

@@ -160,6 +160,7 @@ def test_lanes_matrix_is_refused_by_the_products_that_do_not_take_it():
     m = L.pjds_batch_member(info=ctypes.pointer(info))
     out = ctypes.c_void_p()
     assert lib.pjds_batch_create(1, ctypes.byref(m), 0, L.PJDS_Y_PERMUTED, 0, 8, ctypes.byref(out)) == L.PJDS_ERR_UNSUPPORTED
+    assert lib.pjds_batch_create_xlds(1, ctypes.byref(m), 0, L.PJDS_Y_PERMUTED, 16, 512, ctypes.byref(out)) == L.PJDS_ERR_UNSUPPORTED
     # the product itself takes it (and checks its arrays first)
     assert lib.pjds_spmv(ctypes.byref(info), None, None, None, None, None, None, None, 0, None, None, 0, None) == L.PJDS_ERR_ARG
 
@@ -177,4 +178,11 @@ def test_batch_create_validates_on_the_host():
     assert lib.pjds_batch_create(0, arr, 0, 0, 0, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
     assert lib.pjds_batch_create(1, arr, 0, 0, 9, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
     assert lib.pjds_batch_create(1, arr, 0, 0x40, 0, 0, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert h.value is None
+    # the LDS-staged form: the same member checks, and a halo that is not negative
+    assert lib.pjds_batch_create_xlds(1, arr, 0, 0, 16, -1, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert "x_halo" in L.pjds_last_error()
+    assert lib.pjds_batch_create_xlds(2, arr, 0, 0, 16, 512, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert lib.pjds_batch_create_xlds(1, arr, 0, 0x40, 16, 512, ctypes.byref(h)) == L.PJDS_ERR_ARG
+    assert lib.pjds_batch_create_xlds(1, arr, 7, 0, 16, 512, None) == L.PJDS_ERR_ARG
     assert h.value is None

@@ -300,21 +300,25 @@ def main() -> int:
     if not args.no_extra:
         extra = {}
         # cold Infinity Cache: the median of single products, each after a 1 GiB streaming
-        # pass over another buffer evicts the matrix from the 256 MB MALL
+        # pass over another buffer evicts the matrix and x from the 256 MB MALL
         flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         flush.fill_(1.0)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(21)]
-        for s0, s1 in ev:
-            flush.mul_(1.0)
-            s0.record()
-            step()
-            s1.record()
-        torch.cuda.synchronize()
-        cold = sorted(s0.elapsed_time(s1) for s0, s1 in ev[1:])
-        ms_cold = cold[len(cold) // 2]
-        extra["cold_mall"] = {"reps": len(cold), "median_ms": round(ms_cold, 5),
+
+        def cold_median(fn, reps: int = 20) -> float:
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps + 1)]
+            for s0, s1 in ev:
+                flush.mul_(1.0)
+                s0.record()
+                fn()
+                s1.record()
+            torch.cuda.synchronize()
+            cold = sorted(s0.elapsed_time(s1) for s0, s1 in ev[1:])
+            return cold[len(cold) // 2]
+
+        ms_cold = cold_median(step)
+        extra["cold_mall"] = {"reps": 20, "median_ms": round(ms_cold, 5),
                               "GBps_alg": round(b_alg / ms_cold / 1e6, 1)}
-        del flush
         # same matrix in the comparison formats
         log("ELLPACK-R and CSR legs")
         info_e = EllrMatrix.plan(A)
@@ -344,7 +348,8 @@ def main() -> int:
         extra["pjds_xcd_remap"] = {"ms": round(ms_nr, 5)}
         # many right-hand sides on the same matrix: the tile shape and XCD renumbering tuned
         # per k on two sort windows (256 keeps shared rows of X close; 4096 with renumbering lets
-        # each XCD's L2 keep them); effective GFLOP/s vs the headline single-vector product
+        # each XCD's L2 keep them), and X staged in LDS on windows of 256; effective GFLOP/s vs
+        # the headline single-vector product
         spmmv = {"plain_gflops": round(gflops, 2)}
         from paper_1112_5588_amd import autotune as _at
         for sw_k in (256, 4096):
@@ -357,8 +362,23 @@ def main() -> int:
                                                       y_permuted=True, xcd_remap=rmp), 20, 3)
                 if f"k{k}" not in spmmv or ms_k < spmmv[f"k{k}"]["ms"]:
                     spmmv[f"k{k}"] = {"sort_window": sw_k, "tile": t, "vectors_per_lane": vpl, "xcd_remap": rmp,
+                                      "x_path": "caches",
                                       "ms": round(ms_k, 5), "gflops": round(2 * k * nnz / ms_k / 1e6, 2),
                                       "over_plain": round(2 * k * nnz / ms_k / 1e6 / gflops, 2)}
+                if sw_k == 256:
+                    # X staged in LDS (pjds_spmmv_xlds): one vector tile of up to 8 vectors, since
+                    # 64 KiB holds 1024 rows of 8 FP64 values (512-row tiles) or 2048 rows of 4
+                    t_s = min(k, 8)
+                    tile_s = 1024 if t_s * vbytes <= 32 else 512
+                    ms_s = time_launches(lambda: Mk.spmmv_xlds(X, Y, vectors_per_tile=t_s, vectors_per_lane=4,
+                                                               x_halo=512, tile_rows=tile_s, y_permuted=True), 20, 3)
+                    spmmv[f"k{k}_x_in_lds"] = {"tile": t_s, "tile_rows": tile_s, "x_halo": 512, "ms": round(ms_s, 5),
+                                               "gflops": round(2 * k * nnz / ms_s / 1e6, 2)}
+                    if ms_s < spmmv[f"k{k}"]["ms"]:
+                        spmmv[f"k{k}"] = {"sort_window": sw_k, "tile": t_s, "vectors_per_lane": 4, "xcd_remap": False,
+                                          "x_path": "lds", "tile_rows": tile_s, "x_halo": 512,
+                                          "ms": round(ms_s, 5), "gflops": round(2 * k * nnz / ms_s / 1e6, 2),
+                                          "over_plain": round(2 * k * nnz / ms_s / 1e6 / gflops, 2)}
                 del X, Y
             del Mk
         extra["spmmv"] = spmmv
@@ -574,9 +594,13 @@ def main() -> int:
             pl[label] = {"ms": round(ms_p, 5), "GBps_alg": round(bp / ms_p / 1e6, 1),
                          "nnz_stored": Mp.info.nnz_stored,
                          "padding": round(Mp.info.nnz_stored / P.nnz - 1, 4)}
+            if label == "global_split512":        # cold-cache protocol: x (64 MB) evicted too
+                ms_c = cold_median(lambda: Mp.spmv(xp, yp_, y_permuted=True))
+                pl[label]["cold_mall_median_ms"] = round(ms_c, 5)
+                pl[label]["cold_mall_GBps_alg"] = round(bp / ms_c / 1e6, 1)
             del Mp
         extra["powerlaw"] = pl
-        del P, xp, yp_
+        del P, xp, yp_, flush
         result["extra"] = extra
     if not args.no_batch:
         torch.cuda.empty_cache()

@@ -221,6 +221,23 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
                int32_t dtype, int32_t k, int32_t vectors_per_tile, int32_t vectors_per_lane,
                const void *d_X, void *d_Y, uint32_t flags, void *stream);
 
+/*
+ * Y = A X as pjds_spmmv, with X staged in LDS (the idea of pjds_spmv_xlds for k right-hand
+ * sides).  Needs the block layout and a sort window; t / vectors_per_lane lanes per row must
+ * be 1, 2 or 4.  A 512-thread workgroup owns `tile_rows` consecutive sorted rows (a multiple
+ * of 64; 0 -> max(window, 1024)) and one tile of t right-hand sides; it copies the rows of X
+ * that the original rows of its sort windows cover, widened by x_halo (>= 0) on each side,
+ * for those t vectors into LDS (at most 64 KiB: two workgroups per CU), then reads an X row
+ * from LDS where staged and from global memory otherwise.  The same FMAs in the same order as
+ * pjds_spmmv: results equal it bit for bit, for any halo.  No flag other than PJDS_Y_PERMUTED.
+ * Errors: ERR_ARG (layout, sizes, alignment, halo), ERR_UNSUPPORTED (several lanes per row).
+ */
+int pjds_spmmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                    const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+                    int32_t dtype, int32_t k, int32_t vectors_per_tile, int32_t vectors_per_lane,
+                    const void *d_X, void *d_Y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
+                    void *stream);
+
 /* ---- the product inside an iterative solver ----------------------------------------- */
 /*
  * `steps` steps of the symmetric Lanczos recurrence on a square matrix converted with

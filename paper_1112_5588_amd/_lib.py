@@ -88,6 +88,7 @@ _SIGS = {
     "pjds_workspace_init": [_ip, _i32, _vp, _vp],
     "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "pjds_spmv_axpby": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _u32, _vp],
     "pjds_lanczos_workspace": [_ip, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
@@ -239,6 +240,15 @@ def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, 
                             _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
                             vectors_per_tile, vectors_per_lane, _dev(d_X), _dev(d_Y), flags,
                             _stream(stream)), "pjds_spmmv")
+
+
+def pjds_spmmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,
+                    vectors_per_tile: int, vectors_per_lane: int, d_X, d_Y, x_halo: int, tile_rows: int,
+                    flags: int = 0, stream=None) -> None:
+    _check(lib().pjds_spmmv_xlds(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                                 _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
+                                 vectors_per_tile, vectors_per_lane, _dev(d_X), _dev(d_Y), x_halo,
+                                 tile_rows, flags, _stream(stream)), "pjds_spmmv_xlds")
 
 
 def ellr_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray) -> pjds_info:

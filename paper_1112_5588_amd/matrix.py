@@ -163,6 +163,27 @@ class PjdsMatrix:
                      vectors_per_tile, X, Y, flags, stream, vectors_per_lane)
         return Y
 
+    def spmmv_xlds(self, X: torch.Tensor, Y: torch.Tensor | None = None, vectors_per_tile: int | None = None,
+                   vectors_per_lane: int | None = None, x_halo: int = 512, tile_rows: int = 1024,
+                   y_permuted: bool = False, stream=None) -> torch.Tensor:
+        """Y = A X with X staged in LDS per tile (pjds_spmmv_xlds): the block layout with a sort
+        window; t / vectors_per_lane lanes per row of 1, 2 or 4 (default t: k, at most 4 lanes)."""
+        k = X.shape[1]
+        if vectors_per_lane is None:
+            vectors_per_lane = next(v for v in (4, 2, 1) if k % v == 0)
+        if vectors_per_tile is None:
+            lanes = 1
+            while lanes < 4 and lanes * vectors_per_lane < k:
+                lanes *= 2
+            vectors_per_tile = lanes * vectors_per_lane
+        if Y is None:
+            Y = torch.empty((self.info.n_rows, k), dtype=self.dtype, device=self.device)
+        d = self.d
+        L.pjds_spmmv_xlds(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], k,
+                          vectors_per_tile, vectors_per_lane, X, Y, x_halo, tile_rows,
+                          L.PJDS_Y_PERMUTED if y_permuted else 0, stream)
+        return Y
+
     def footprint_bytes(self) -> int:
         """Device bytes of the format: values, column indices, row lengths, offsets, perm."""
         i = self.info

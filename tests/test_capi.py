@@ -157,6 +157,7 @@ def test_lanes_matrix_is_refused_by_the_products_that_do_not_take_it():
     lib = L.lib()
     assert lib.pjds_spmmv(ctypes.byref(info), None, None, None, None, None, 0, 4, 4, 1, None, None, 0, None) == L.PJDS_ERR_UNSUPPORTED
     assert lib.pjds_spmv_xlds(ctypes.byref(info), None, None, None, None, None, 0, None, None, 512, 512, 0, None) == L.PJDS_ERR_UNSUPPORTED
+    assert lib.pjds_spmmv_xlds(ctypes.byref(info), None, None, None, None, None, 0, 4, 4, 4, None, None, 512, 512, 0, None) == L.PJDS_ERR_UNSUPPORTED
     m = L.pjds_batch_member(info=ctypes.pointer(info))
     out = ctypes.c_void_p()
     assert lib.pjds_batch_create(1, ctypes.byref(m), 0, L.PJDS_Y_PERMUTED, 0, 8, ctypes.byref(out)) == L.PJDS_ERR_UNSUPPORTED
@@ -186,3 +187,26 @@ def test_batch_create_validates_on_the_host():
     assert lib.pjds_batch_create_xlds(1, arr, 0, 0x40, 16, 512, ctypes.byref(h)) == L.PJDS_ERR_ARG
     assert lib.pjds_batch_create_xlds(1, arr, 7, 0, 16, 512, None) == L.PJDS_ERR_ARG
     assert h.value is None
+
+
+def test_spmmv_xlds_validates_on_the_host():
+    A = synth.random_csr(3000, 3000, 5, max_len=20)
+    lib = L.lib()
+    win = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 64, 256, L.PJDS_LAYOUT_BLOCK, 0)
+    glob = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 64, 0, L.PJDS_LAYOUT_BLOCK, 0)
+    jd = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 64, 0, 0, 0)
+
+    def call(info, k=4, t=4, vpl=4, halo=512, tile=1024, flags=0):
+        return lib.pjds_spmmv_xlds(ctypes.byref(info), None, None, None, None, None, 0, k, t, vpl, None, None,
+                                   halo, tile, flags, None)
+    assert call(glob) == L.PJDS_ERR_ARG and "sort window" in L.pjds_last_error()
+    assert call(jd) == L.PJDS_ERR_ARG
+    assert call(win, vpl=3) == L.PJDS_ERR_ARG
+    assert call(win, k=6, t=8, vpl=4) == L.PJDS_ERR_ARG          # k not a multiple of the lane width
+    assert call(win, k=32, t=32, vpl=4) == L.PJDS_ERR_ARG        # eight lanes per row
+    assert call(win, halo=-1) == L.PJDS_ERR_ARG
+    assert call(win, tile=100) == L.PJDS_ERR_ARG
+    assert call(win, flags=L.PJDS_XCD_REMAP) == L.PJDS_ERR_ARG
+    assert call(win, k=0) == L.PJDS_ERR_ARG
+    # valid arguments reach the device-array check
+    assert call(win) == L.PJDS_ERR_ARG and "NULL" in L.pjds_last_error()

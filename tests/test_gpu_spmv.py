@@ -231,6 +231,53 @@ def test_spmmv_xcd_renumbering_is_bitwise_identical(window):
     assert oracle.rel_l2(host(Y1), ref) <= 1e-12
 
 
+# ------------------------------------------------------------------ SpMMV with X staged in LDS
+
+@pytest.mark.parametrize("k,t,vpl", [(1, 1, 1), (4, 4, 4), (8, 8, 4), (12, 8, 4), (16, 16, 4), (32, 16, 4),
+                                     (6, 4, 2), (3, 4, 1)])
+@pytest.mark.parametrize("window,halo,tile", [(256, 512, 1024), (128, 0, 256), (512, 3000, 512), (192, 700, 320)])
+def test_spmmv_xlds_equals_spmmv_bitwise(k, t, vpl, window, halo, tile):
+    # ragged row count (partial tile, partial wave), partial vector tiles (k = 12 with t = 8,
+    # lanes past k), halos from none to wider than the 64 KiB cap, tiles that divide the
+    # window, are divided by it, or neither; the same FMAs in the same order as pjds_spmmv
+    A = synth.hh_like(30011, seed=43, band=600)
+    X = dev(synth.dense_x(A.n_cols, 43, k=k).reshape(A.n_cols, k))
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=window, keep_host=True)
+    for yp in (False, True):
+        Y0 = M.spmmv(X, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=yp)
+        Y1 = M.spmmv_xlds(X, vectors_per_tile=t, vectors_per_lane=vpl, x_halo=halo, tile_rows=tile, y_permuted=yp)
+        assert torch.equal(Y0, Y1)
+    ref = oracle.csr_spmmv(A, host(X))[M.host["perm"]]
+    assert oracle.rel_l2(host(Y1), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("b_r", [32, 128])
+def test_spmmv_xlds_block_heights_float32_and_small(b_r):
+    for n in (300, 5000):
+        A = synth.hh_like(n, seed=44).astype(np.float32)
+        X = synth.dense_x(A.n_cols, 44, k=4).reshape(A.n_cols, 4).astype(np.float32)
+        M = PjdsMatrix.from_csr(A, block_height=b_r, layout="block", sort_window=128)
+        Y0 = M.spmmv(dev(X, torch.float32), vectors_per_tile=4, vectors_per_lane=4)
+        Y1 = M.spmmv_xlds(dev(X, torch.float32), vectors_per_tile=4, vectors_per_lane=4, x_halo=256, tile_rows=256)
+        assert torch.equal(Y0, Y1)
+        ref = oracle.csr_spmmv(A.astype(np.float64), X.astype(np.float64))
+        assert oracle.rel_l2(host(Y1), ref) <= 1e-5
+
+
+def test_spmmv_xlds_refusals():
+    A = synth.hh_like(2000, seed=45)
+    X = dev(np.ones((A.n_cols, 4)))
+    with pytest.raises(L.PjdsError):       # a global sort: nothing to stage by window
+        PjdsMatrix.from_csr(A, layout="block").spmmv_xlds(X)
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=256)
+    with pytest.raises(L.PjdsError):       # eight lanes per row
+        M.spmmv_xlds(dev(np.ones((A.n_cols, 32))), vectors_per_tile=32, vectors_per_lane=4)
+    with pytest.raises(L.PjdsError):
+        M.spmmv_xlds(X, x_halo=-1)
+    with pytest.raises(L.PjdsError):
+        M.spmmv_xlds(X, tile_rows=100)
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 @pytest.fixture(scope="module")

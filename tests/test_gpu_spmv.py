@@ -337,6 +337,23 @@ def test_headline_configuration_full_size(hh_full, dtype):
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True))
 
 
+@pytest.mark.parametrize("k,t,tile", [(4, 4, 1024), (8, 8, 512)])
+def test_spmmv_xlds_full_size(hh_full, k, t, tile):
+    # the benchmark's staged SpMMV launches on the full HH-like matrix: bitwise against the
+    # unstaged kernel over all of Y, sampled rows against the oracle
+    A = hh_full
+    X_np = synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)
+    X = dev(X_np)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=256, keep_host=True)
+    Y = M.spmmv_xlds(X, vectors_per_tile=t, vectors_per_lane=4, x_halo=512, tile_rows=tile, y_permuted=True)
+    assert torch.equal(Y, M.spmmv(X, vectors_per_tile=t, vectors_per_lane=4, y_permuted=True))
+    perm = M.host["perm"]
+    rows_p = np.unique(np.concatenate([np.arange(256), np.arange(A.n_rows - 256, A.n_rows),
+                                       (synth.uniform01(82, 1, 2048) * A.n_rows).astype(np.int64)]))
+    ref = oracle.csr_spmmv(sampled_rows(A, perm[rows_p]), X_np)
+    assert oracle.rel_l2(host(Y)[rows_p], ref) <= 1e-12
+
+
 def test_powerlaw_full_size_sampled():
     A = synth.powerlaw(1 << 23, seed=3)
     x = synth.dense_x(A.n_cols, 3)

@@ -228,7 +228,8 @@ int pjds_spmmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d
  * of 64; 0 -> max(window, 1024)) and one tile of t right-hand sides; it copies the rows of X
  * that the original rows of its sort windows cover, widened by x_halo (>= 0) on each side,
  * for those t vectors into LDS (at most 64 KiB: two workgroups per CU), then reads an X row
- * from LDS where staged and from global memory otherwise.  The same FMAs in the same order as
+ * from LDS where staged and from global memory otherwise.  Row tiles go to the XCDs in runs
+ * of 16, as in pjds_spmv_xlds.  The same FMAs in the same order as
  * pjds_spmmv: results equal it bit for bit, for any halo.  No flag other than PJDS_Y_PERMUTED.
  * Errors: ERR_ARG (layout, sizes, alignment, halo), ERR_UNSUPPORTED (several lanes per row).
  */

@@ -48,6 +48,16 @@ __device__ __forceinline__ int64_t wave_first(int64_t v) {
 template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
+// Row tiles go to the 8 XCDs (hardware: workgroup b on XCD b % 8) in runs of 16 consecutive
+// tiles, so neighbours that stage overlapping X rows share an L2; blocks of an incomplete last
+// round keep their number.  A bijection on [0, grid).
+__device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t grid) {
+    constexpr uint32_t kXcds = 8, kGroup = 16;
+    const uint32_t x = b % kXcds, q = b / kXcds;
+    if (q / kGroup >= grid / (kXcds * kGroup)) return b;
+    return (q / kGroup) * (kXcds * kGroup) + x * kGroup + q % kGroup;
+}
+
 template <class T, int BR, int LPR, int VPL>
 __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile, int32_t cap,
@@ -62,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
     const int v0 = int(blockIdx.y) * TV;           // first vector of the tile
-    const int64_t r0 = int64_t(blockIdx.x) * tile;
+    const int64_t r0 = int64_t(xcd_group(blockIdx.x, gridDim.x)) * tile;
     const int64_t r1 = min(r0 + tile, n_pad);
     const int64_t lo_r = r0 / window * window;
     const int64_t hi_r = (r1 + window - 1) / window * window;

@@ -303,7 +303,8 @@ int pjds_batch_create(int32_t n_members, const pjds_batch_member *members, int32
 /*
  * A persistent batch (as PJDS_BATCH_PERSISTENT) whose kernel stages x in LDS, the idea of
  * pjds_spmv_xlds applied per tile: 512-thread workgroups pull tiles of `groups_per_tile` wave
- * groups (<= 0 -> 16, i.e. 1024 rows); a workgroup copies x[lo, hi) of its member into LDS,
+ * groups (<= 0 -> 32, i.e. 2048 rows, when every member is sorted in windows of whole 128-row
+ * groups, else 8); a workgroup copies x[lo, hi) of its member into LDS,
  * where [lo, hi) are the original rows of the sort windows its sorted rows lie in (the whole
  * member for a global sort) widened by `x_halo` (>= 0) on each side and clipped to the
  * member's columns, then its waves pull the tile's wave groups and read x from LDS wherever

@@ -251,6 +251,20 @@ def test_spmmv_xlds_equals_spmmv_bitwise(k, t, vpl, window, halo, tile):
     assert oracle.rel_l2(host(Y1), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("k,t", [(4, 4), (8, 8)])
+def test_spmmv_xlds_xcd_groups_with_a_tail(k, t):
+    # 70001 rows in 256-row tiles: 274 workgroups, two whole rounds of 16 tiles per XCD and
+    # 18 left in hardware order; every row computed once, bitwise as pjds_spmmv
+    A = synth.hh_like(70001, seed=46)
+    X = dev(synth.dense_x(A.n_cols, 46, k=k).reshape(A.n_cols, k))
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=256, keep_host=True)
+    assert -(-M.info.n_pad // 256) == 274
+    Y = torch.full((A.n_rows, k), float("nan"), dtype=torch.float64, device="cuda")
+    M.spmmv_xlds(X, Y, vectors_per_tile=t, vectors_per_lane=4, x_halo=512, tile_rows=256)
+    assert torch.equal(Y, M.spmmv(X, vectors_per_tile=t, vectors_per_lane=4))
+    assert oracle.rel_l2(host(Y), oracle.csr_spmmv(A, host(X))) <= 1e-12
+
+
 @pytest.mark.parametrize("b_r", [32, 128])
 def test_spmmv_xlds_block_heights_float32_and_small(b_r):
     for n in (300, 5000):

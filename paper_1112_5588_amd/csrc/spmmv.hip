@@ -1,6 +1,6 @@
 // SpMMV with the right-hand sides staged in LDS: Y = A X for k vectors, X and Y row-major
-// (X[c * k + v]), the matrix in pJDS block layout sorted in windows (Sect. 2.1; the batching of
-// several right-hand sides per matrix entry is the extension the survey of the method lists).
+// (X[c * k + v]), the matrix in pJDS block layout sorted in windows (Sect. 2.1; applying each
+// matrix entry to several right-hand sides is an extension beyond the paper's single vector).
 //
 // A workgroup owns `tile` consecutive sorted rows.  Sorting never moves a row out of its window
 // of original rows, so the tile's rows lie in the original rows of the windows it touches; the

@@ -14,7 +14,15 @@ the product, 12 B per non-zero (value + column index) plus 8 B per row for x and
 row for y, divided by the measured time per product.
 
     python bench.py [--steps K] [--warmup W] [--workload hh_like|laplacian|powerlaw]
-                    [--dtype f64|f32] [--no-cpu] [--no-extra]
+                    [--dtype f64|f32] [--sort-window W] [--x-halo H] [--tile-rows T] [--one-row]
+                    [--lanes T] [--xcd-remap] [--no-cpu] [--no-extra] [--no-batch]
+
+Besides the headline line's own fields, `extra` holds the comparison legs (cold Infinity Cache,
+ELLPACK-R, CSR, SpMMV with X through the caches or staged in LDS, the 128 x 128 Laplacian's
+SpMMV against single products, the exhaustive and learned tuners, Lanczos steps, the host-link
+model, lanes per row, the local/non-local split, FP32 and the power-law matrix) and `batch` the
+512-matrix leg (persistent kernel with x through the caches or staged in LDS, per-member graph,
+direct launches).
 """
 from __future__ import annotations
 

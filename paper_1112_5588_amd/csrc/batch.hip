@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "common.h"
+#include "device.h"
 
 namespace pjds {
 namespace {
@@ -51,18 +52,6 @@ struct Member {                    // device-side descriptor of one batch member
 struct Tile {                      // wave groups [g0, g1) of member m
     int32_t m, g0, g1, pad;
 };
-
-// Rows are sorted longest first inside windows that hold whole waves, so lane 0 of a wave
-// group holds its longest row (the loop bound, and the slot that lanes past their own row
-// re-read).
-__device__ __forceinline__ int64_t wave_first(int64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
-    return int64_t((uint64_t(hi) << 32) | lo);
-}
-
-template <class T>
-__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 
 // x gathered from global memory
 template <class T>
@@ -138,12 +127,6 @@ __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_pe
 // are neighbours at every step, so one 2-wide load brings both values and one both indices.
 // Row i is the longer, so lane 0's pair serves lanes that are done.  Same FMAs in the same
 // order per row as wave_group.
-template <class T>
-struct Pair2;
-template <>
-struct Pair2<double> { typedef double type __attribute__((ext_vector_type(2))); };
-template <>
-struct Pair2<float> { typedef float type __attribute__((ext_vector_type(2))); };
 typedef int32_t Int2 __attribute__((ext_vector_type(2)));
 
 template <int U, bool CLAMP, class T, bool JD, int BR, class XA>
@@ -151,7 +134,7 @@ __device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, in
                                        int64_t base_lead, const int64_t *__restrict__ off,
                                        const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
                                        const XA &x) {
-    typedef typename Pair2<T>::type V2;
+    typedef typename VecOf<T, 2>::type V2;
     V2 v[U];
     Int2 c[U];
 #pragma unroll

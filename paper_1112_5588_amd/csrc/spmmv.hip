@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "device.h"
 #include "launch.h"
 
 namespace pjds {
@@ -23,40 +24,6 @@ constexpr int kThreads = 512;            // threads of a workgroup
 constexpr int kStage = 8;                // X values in flight per thread while staging
 constexpr int64_t kMaxLds = 64 * 1024;   // staged X per workgroup (two workgroups per CU)
 
-template <class T, int VPL>
-struct Vec;
-template <class T>
-struct Vec<T, 1> { typedef T type; };
-template <>
-struct Vec<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <>
-struct Vec<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <>
-struct Vec<double, 4> { typedef double type __attribute__((ext_vector_type(4))); };
-template <>
-struct Vec<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
-
-// Rows are sorted longest first inside windows that hold whole waves: lane 0's row bounds the
-// wave's loop, and lanes past their own row re-read lane 0's slot (never padding).
-__device__ __forceinline__ int wave_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t wave_first(int64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
-    return int64_t((uint64_t(hi) << 32) | lo);
-}
-
-template <class T>
-__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
-
-// Row tiles go to the 8 XCDs (hardware: workgroup b on XCD b % 8) in runs of 16 consecutive
-// tiles, so neighbours that stage overlapping X rows share an L2; blocks of an incomplete last
-// round keep their number.  A bijection on [0, grid).
-__device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t grid) {
-    constexpr uint32_t kXcds = 8, kGroup = 16;
-    const uint32_t x = b % kXcds, q = b / kXcds;
-    if (q / kGroup >= grid / (kXcds * kGroup)) return b;
-    return (q / kGroup) * (kXcds * kGroup) + x * kGroup + q % kGroup;
-}
 
 template <class T, int BR, int LPR, int VPL>
 __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
@@ -64,7 +31,7 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     int32_t k, const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p, const int32_t *__restrict__ perm,
     const T *__restrict__ X, T *__restrict__ Y, uint32_t flags) {
-    typedef typename Vec<T, VPL>::type V;
+    typedef typename VecOf<T, VPL>::type V;
     constexpr int TV = LPR * VPL;                  // vectors of one vector tile
     constexpr int RW = kWave / LPR;                // rows of a wave
     constexpr int RP = kThreads / LPR;             // rows of the workgroup per pass

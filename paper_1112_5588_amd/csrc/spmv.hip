@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "device.h"
 #include "launch.h"
 
 namespace pjds {
@@ -40,7 +41,6 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 #endif
 constexpr int kUnroll = PJDS_UNROLL;      // independent entries in flight per lane
 constexpr int kStage = 8;                 // x values in flight per thread while staging into LDS
-constexpr uint32_t kXcds = 8;
 
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
     // Hardware hands workgroup b to XCD b % 8; give XCD x the contiguous logical range
@@ -53,19 +53,8 @@ __device__ __forceinline__ uint32_t logical_block(uint32_t flags) {
     return (flags & PJDS_XCD_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
 }
 
-// Tiles of the LDS product are handed out in runs of kXcdGroup consecutive tiles per XCD:
-// neighbouring tiles, whose staged x ranges overlap by the halo, then share one L2, while all
-// eight XCDs still stream nearby parts of the matrix (whole contiguous ranges per XCD spread
-// the streams too far apart).  The blocks of an incomplete last round keep their own number.
-// A bijection on [0, grid).
-constexpr uint32_t kXcdGroup = 16;
-
-__device__ __forceinline__ uint32_t xcd_group(uint32_t b, uint32_t grid) {
-    const uint32_t x = b % kXcds, k = b / kXcds;
-    if (k / kXcdGroup >= grid / (kXcds * kXcdGroup)) return b;
-    return (k / kXcdGroup) * (kXcds * kXcdGroup) + x * kXcdGroup + k % kXcdGroup;
-}
-
+// Tiles of the LDS product: contiguous ranges per XCD with PJDS_XCD_REMAP, else runs of
+// kXcdGroup tiles per XCD.
 __device__ __forceinline__ uint32_t tile_block(uint32_t flags) {
     return (flags & PJDS_XCD_REMAP) ? xcd_remap(blockIdx.x, gridDim.x) : xcd_group(blockIdx.x, gridDim.x);
 }
@@ -74,19 +63,6 @@ __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
     return __builtin_amdgcn_readfirstlane(v);
-}
-
-template <class T>
-__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
-
-// Rows are sorted by length, longest first, inside windows that hold whole waves, so lane 0
-// of a wave holds the wave's longest row: its length bounds the wave's loop and its slot is
-// the one lanes past their own row re-read.  Both are wave-uniform values.
-__device__ __forceinline__ int wave_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t wave_first(int64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
-    return int64_t((uint64_t(hi) << 32) | lo);
 }
 
 // Lowest lane of the wave whose row is the longest (len == m, m > 0); for unsorted rows.
@@ -520,18 +496,6 @@ __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
 // from the interleaved X (X[c*k + v]) with one VPL-wide load.  A matrix entry is therefore
 // loaded once per tile, a wave covers R = 64/LPR rows, and a gather instruction reads LPR *
 // VPL contiguous values per row.  Tiles over k run in gridDim.y.
-template <class T, int VPL>
-struct VecOf;
-template <class T>
-struct VecOf<T, 1> { typedef T type; };
-template <>
-struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <>
-struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <>
-struct VecOf<double, 4> { typedef double type __attribute__((ext_vector_type(4))); };
-template <>
-struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
 
 template <class T, bool JD, int BR, int LPR, int VPL>
 __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(

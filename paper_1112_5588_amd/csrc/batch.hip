@@ -67,8 +67,7 @@ struct XStaged {
     const T *x;
     uint32_t lo, n;
     __device__ __forceinline__ T operator()(int32_t c) const {
-        const uint32_t d = uint32_t(c) - lo;
-        return d < n ? lds[d] : x[c];
+        return staged_or_global<T>(lds, uint32_t(c) - lo, n, 1, x, c);
     }
 };
 

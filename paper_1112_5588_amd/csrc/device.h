@@ -23,6 +23,21 @@ __device__ __forceinline__ int64_t wave_first(int64_t v) {
     return int64_t((uint64_t(hi) << 32) | lo);
 }
 
+// A value (or VPL-wide vector V) from LDS when its staged row d is below n, else from global
+// memory at x + xoff.  The LDS row holds `stride` vectors, the first at `staged`.  The two
+// loads are separate instructions -- a ds_read for the staged lanes and an exec-masked global
+// load for the others -- so no generic (flat) load serves both; the LDS index is clamped to
+// row 0 for lanes that do not use it.
+template <class V, class T>
+__device__ __forceinline__ V staged_or_global(const T *staged, uint32_t d, uint32_t n, uint32_t stride,
+                                              const T *x, int64_t xoff) {
+    typedef __attribute__((address_space(3))) const V LdsV;
+    const bool in = d < n;
+    V v = ((const LdsV *)(staged))[(in ? d : 0u) * stride];
+    if (!in) v = *reinterpret_cast<const V *>(x + xoff);
+    return v;
+}
+
 // VPL adjacent values as one vector: one wide load or store.
 template <class T, int VPL>
 struct VecOf;

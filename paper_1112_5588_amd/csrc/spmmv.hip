@@ -93,9 +93,8 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
                 V xv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t d = uint32_t(a_c[u]) - uint32_t(lo);
-                    xv[u] = d < uint32_t(nr) ? *reinterpret_cast<const V *>(xs + int64_t(d) * TV + q0)
-                                             : *reinterpret_cast<const V *>(X + int64_t(a_c[u]) * k + vc);
+                    xv[u] = staged_or_global<V>(xs + q0, uint32_t(a_c[u]) - uint32_t(lo), uint32_t(nr), LPR, X,
+                                                int64_t(a_c[u]) * k + vc);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {

@@ -98,8 +98,7 @@ struct XStaged {
     int64_t lo;
     uint32_t n;
     __device__ T operator()(int32_t c) const {
-        const uint32_t d = uint32_t(int64_t(c) - lo);
-        return d < n ? lds[d] : x[c];
+        return staged_or_global<T>(lds, uint32_t(int64_t(c) - lo), n, 1, x, c);
     }
 };
 

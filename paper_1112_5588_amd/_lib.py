@@ -159,6 +159,72 @@ def _dev(t):
     return t.data_ptr() or None
 
 
+def _dev_vec(t, n: int, code: int, name: str, like=None, required: bool = True):
+    """Checks a device array argument before its pointer goes to a kernel: a torch tensor on
+    the GPU (on ``like``'s device), of the kernel's value type ``code`` and with at least n
+    elements.  A kernel would otherwise read or write past its end, or reinterpret its bytes."""
+    if t is None:
+        if required and n > 0:
+            raise ValueError(f"{name} is required")
+        return None
+    if not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if code is not None and _dtype_code(t.dtype) != code:
+        raise TypeError(f"{name} has dtype {t.dtype}, the matrix values are {'float64' if code == PJDS_F64 else 'float32'}")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+    if like is not None and t.device != like.device:
+        raise ValueError(f"{name} is on {t.device}, the matrix on {like.device}")
+    return t
+
+
+def _dev_int(t, n: int, dtype, name: str, like=None, required: bool = True):
+    """An index array on the device: its integer type and at least n elements."""
+    if t is None:
+        if required and n > 0:
+            raise ValueError(f"{name} is required")
+        return None
+    if not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if str(t.dtype).replace("torch.", "") != np.dtype(dtype).name:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {np.dtype(dtype).name}")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+    if like is not None and t.device != like.device:
+        raise ValueError(f"{name} is on {t.device}, the matrix on {like.device}")
+    return t
+
+
+def _host_arr(a, n: int, dtype, name: str, required: bool = True):
+    """A host array argument: its type and at least n elements."""
+    if a is None:
+        if required and n > 0:
+            raise ValueError(f"{name} is required")
+        return
+    if dtype is not None and a.dtype != np.dtype(dtype):
+        raise TypeError(f"{name} has dtype {a.dtype}, expected {np.dtype(dtype)}")
+    if a.size < n:
+        raise ValueError(f"{name} holds {a.size} elements, {n} needed")
+
+
+def _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y, k: int = 1,
+                   need_perm: bool = True):
+    """The device operands of a product on a pJDS matrix, checked against its sizes: values
+    and x, y of one type, x of n_cols * k and y of n_rows * k elements, index arrays of the
+    planned lengths.  Returns the dtype code."""
+    if d_y is None:
+        raise ValueError("y is required")
+    code = _dtype_code(d_y.dtype)
+    _dev_vec(d_y, info.n_rows * k, code, "y")
+    _dev_vec(d_x, info.n_cols * k, code, "x", like=d_y)
+    _dev_vec(d_val_p, info.nnz_stored, code, "val_p", like=d_y)
+    _dev_int(d_col_p, info.nnz_stored, np.int32, "col_p", like=d_y)
+    _dev_int(d_row_len, info.n_pad, np.int32, "row_len", like=d_y)
+    _dev_int(d_offsets, info.n_offsets, np.int64, "offsets", like=d_y)
+    _dev_int(d_perm, info.n_rows, np.int32, "perm", like=d_y, required=need_perm)
+    return code
+
+
 def _stream(s):
     if s is None:
         import torch
@@ -199,6 +265,15 @@ def pjds_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray, block_height: int =
 
 def pjds_convert(info: pjds_info, row_ptr, col_idx, val, perm, row_len, offsets, col_p, val_p,
                  sched=None) -> None:
+    _host_arr(row_ptr, info.n_rows + 1, np.int64, "row_ptr")
+    _host_arr(col_idx, info.nnz, np.int32, "col_idx")
+    _host_arr(val, info.nnz, None, "val")
+    _host_arr(perm, info.n_rows, np.int32, "perm")
+    _host_arr(row_len, info.n_pad, np.int32, "row_len")
+    _host_arr(offsets, info.n_offsets, np.int64, "offsets")
+    _host_arr(col_p, info.nnz_stored, np.int32, "col_p")
+    _host_arr(val_p, info.nnz_stored, val.dtype, "val_p")
+    _host_arr(sched, 4 * info.n_chunks, np.int32, "sched", required=info.n_chunks > 0)
     _check(lib().pjds_convert(ctypes.byref(info), _host(row_ptr, np.int64), _host(col_idx, np.int32),
                               _host(val), _dtype_code(val.dtype), _host(perm, np.int32),
                               _host(row_len, np.int32), _host(offsets, np.int64),
@@ -220,6 +295,9 @@ def pjds_workspace_init(info: pjds_info, dtype, d_work, stream=None) -> None:
 
 def pjds_spmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work,
               d_x, d_y, flags: int = 0, stream=None) -> None:
+    _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
+                   need_perm=not flags & PJDS_Y_PERMUTED)
+    _dev_int(d_sched, 4 * info.n_chunks, np.int32, "sched", like=d_y, required=info.n_chunks > 0)
     _check(lib().pjds_spmv(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                            _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
                            _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), flags, _stream(stream)),
@@ -228,6 +306,8 @@ def pjds_spmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d
 
 def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
                    x_halo: int, tile_rows: int = 0, flags: int = 0, stream=None) -> None:
+    _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
+                   need_perm=not flags & PJDS_Y_PERMUTED)
     _check(lib().pjds_spmv_xlds(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                                 _dev(d_val_p), _dev(d_perm), _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y),
                                 x_halo, tile_rows, flags, _stream(stream)), "pjds_spmv_xlds")
@@ -236,6 +316,8 @@ def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_pe
 def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,
                vectors_per_tile: int, d_X, d_Y, flags: int = 0, stream=None,
                vectors_per_lane: int = 1) -> None:
+    _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_X, d_Y, k=max(k, 0),
+                   need_perm=not flags & PJDS_Y_PERMUTED)
     _check(lib().pjds_spmmv(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                             _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
                             vectors_per_tile, vectors_per_lane, _dev(d_X), _dev(d_Y), flags,
@@ -245,6 +327,8 @@ def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, 
 def pjds_spmmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,
                     vectors_per_tile: int, vectors_per_lane: int, d_X, d_Y, x_halo: int, tile_rows: int,
                     flags: int = 0, stream=None) -> None:
+    _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_X, d_Y, k=max(k, 0),
+                   need_perm=not flags & PJDS_Y_PERMUTED)
     _check(lib().pjds_spmmv_xlds(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                                  _dev(d_val_p), _dev(d_perm), _dtype_code(d_Y.dtype), k,
                                  vectors_per_tile, vectors_per_lane, _dev(d_X), _dev(d_Y), x_halo,
@@ -258,35 +342,71 @@ def ellr_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray) -> pjds_info:
 
 
 def ellr_convert(info: pjds_info, row_ptr, col_idx, val, rowmax, col_e, val_e) -> None:
+    _host_arr(row_ptr, info.n_rows + 1, np.int64, "row_ptr")
+    _host_arr(col_idx, info.nnz, np.int32, "col_idx")
+    _host_arr(val, info.nnz, None, "val")
+    _host_arr(rowmax, info.n_pad, np.int32, "rowmax")
+    _host_arr(col_e, info.nnz_stored, np.int32, "col_e")
+    _host_arr(val_e, info.nnz_stored, val.dtype, "val_e")
     _check(lib().ellr_convert(ctypes.byref(info), _host(row_ptr, np.int64), _host(col_idx, np.int32),
                               _host(val), _dtype_code(val.dtype), _host(rowmax, np.int32),
                               _host(col_e, np.int32), _host(val_e)), "ellr_convert")
 
 
 def ellr_spmv(info: pjds_info, d_rowmax, d_col_e, d_val_e, d_x, d_y, stream=None) -> None:
+    if d_y is None:
+        raise ValueError("y is required")
+    code = _dtype_code(d_y.dtype)
+    _dev_vec(d_y, info.n_rows, code, "y")
+    _dev_vec(d_x, info.n_cols, code, "x", like=d_y)
+    _dev_vec(d_val_e, info.nnz_stored, code, "val_e", like=d_y)
+    _dev_int(d_col_e, info.nnz_stored, np.int32, "col_e", like=d_y)
+    _dev_int(d_rowmax, info.n_pad, np.int32, "rowmax", like=d_y)
     _check(lib().ellr_spmv(ctypes.byref(info), _dev(d_rowmax), _dev(d_col_e), _dev(d_val_e),
                            _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), _stream(stream)), "ellr_spmv")
 
 
 def csr_spmv(n_rows: int, n_cols: int, d_row_ptr, d_col, d_val, d_x, d_y, variant: int = 1,
-             stream=None) -> None:
+             stream=None, nnz: int | None = None) -> None:
+    """``nnz`` (optional, the caller's count of entries) checks the sizes of col and val."""
+    if d_y is None:
+        raise ValueError("y is required")
+    code = _dtype_code(d_y.dtype)
+    _dev_vec(d_y, n_rows, code, "y")
+    _dev_vec(d_x, n_cols, code, "x", like=d_y)
+    _dev_int(d_row_ptr, n_rows + 1, np.int64, "row_ptr", like=d_y)
+    if nnz is not None:
+        _dev_vec(d_val, nnz, code, "val", like=d_y)
+        _dev_int(d_col, nnz, np.int32, "col", like=d_y)
     _check(lib().csr_spmv(n_rows, n_cols, _dev(d_row_ptr), _dev(d_col), _dev(d_val),
                           _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), variant, _stream(stream)),
            "csr_spmv")
 
 
 def pjds_probe(mode: int, d_in, d_out, n: int, stream=None) -> None:
+    _dev_vec(d_in, n, PJDS_F64, "in")
+    _dev_vec(d_out, n if mode == 1 else 4096, PJDS_F64, "out", like=d_in)
     _check(lib().pjds_probe(mode, _dev(d_in), _dev(d_out), n, _stream(stream)), "pjds_probe")
+
+
+def _batch_members(members: list, flags: int):
+    """The C array of batch members, each member's operands checked against its sizes."""
+    arr = (pjds_batch_member * len(members))()
+    for k, (info, rl, off, cp, vp, perm, x, y) in enumerate(members):
+        try:
+            _pjds_operands(info, rl, off, cp, vp, perm, x, y, need_perm=not flags & PJDS_Y_PERMUTED)
+        except (TypeError, ValueError) as e:
+            raise type(e)(f"batch member {k}: {e}") from None
+        arr[k] = pjds_batch_member(ctypes.pointer(info), _dev(rl), _dev(off), _dev(cp), _dev(vp),
+                                   _dev(perm), _dev(x), _dev(y))
+    return arr
 
 
 def pjds_batch_create(members: list, dtype, flags: int = 0, mode: int = PJDS_BATCH_PERSISTENT,
                       groups_per_tile: int = 0) -> int:
     """members: list of (info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y).
     Returns the opaque handle (an integer address)."""
-    arr = (pjds_batch_member * len(members))()
-    for k, (info, rl, off, cp, vp, perm, x, y) in enumerate(members):
-        arr[k] = pjds_batch_member(ctypes.pointer(info), _dev(rl), _dev(off), _dev(cp), _dev(vp),
-                                   _dev(perm), _dev(x), _dev(y))
+    arr = _batch_members(members, flags)
     h = _vp()
     _check(lib().pjds_batch_create(len(members), arr, _dtype_code(dtype), flags, mode,
                                    groups_per_tile, ctypes.byref(h)), "pjds_batch_create")
@@ -296,10 +416,7 @@ def pjds_batch_create(members: list, dtype, flags: int = 0, mode: int = PJDS_BAT
 def pjds_batch_create_xlds(members: list, dtype, flags: int = 0, groups_per_tile: int = 0,
                            x_halo: int = 4096) -> int:
     """Like pjds_batch_create (persistent mode) with x staged in LDS per tile."""
-    arr = (pjds_batch_member * len(members))()
-    for k, (info, rl, off, cp, vp, perm, x, y) in enumerate(members):
-        arr[k] = pjds_batch_member(ctypes.pointer(info), _dev(rl), _dev(off), _dev(cp), _dev(vp),
-                                   _dev(perm), _dev(x), _dev(y))
+    arr = _batch_members(members, flags)
     h = _vp()
     _check(lib().pjds_batch_create_xlds(len(members), arr, _dtype_code(dtype), flags, groups_per_tile,
                                         x_halo, ctypes.byref(h)), "pjds_batch_create_xlds")
@@ -339,29 +456,62 @@ def mlp_workspace_size(d_in: int, d_out: int, batch: int) -> int:
     return n.value
 
 
+def _mlp_operands(d_params, d_in: int, d_out: int, d_X, batch_outputs: dict) -> None:
+    """The tuner network's device operands: float32, params of the planned count, X of
+    batch x d_in and each named output of batch x (its width)."""
+    n = mlp_param_count(d_in, d_out)
+    _dev_vec(d_params, n, PJDS_F32, "params")
+    batch = d_X.shape[0] if d_X is not None else 0
+    _dev_vec(d_X, batch * d_in, PJDS_F32, "X", like=d_params)
+    for name, (t, width, code) in batch_outputs.items():
+        if code is None:
+            _dev_int(t, batch * width, np.int32, name, like=d_params, required=False)
+        else:
+            _dev_vec(t, batch * width, code, name, like=d_params, required=False)
+
+
 def mlp_forward(d_params, d_in: int, d_out: int, d_X, d_P, stream=None) -> None:
+    _mlp_operands(d_params, d_in, d_out, d_X, {"P": (d_P, d_out, PJDS_F32)})
+    _dev_vec(d_P, d_X.shape[0] * d_out, PJDS_F32, "P")
     _check(lib().mlp_forward(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_P),
                              _stream(stream)), "mlp_forward")
 
 
 def mlp_backward(d_params, d_in: int, d_out: int, d_X, d_T, d_M, d_grad, d_loss, d_work, stream=None) -> None:
+    _mlp_operands(d_params, d_in, d_out, d_X, {"T": (d_T, d_out, PJDS_F32), "M": (d_M, d_out, PJDS_F32)})
+    _dev_vec(d_T, d_X.shape[0] * d_out, PJDS_F32, "T")
+    _dev_vec(d_grad, mlp_param_count(d_in, d_out), PJDS_F32, "grad", like=d_params)
+    ws = mlp_workspace_size(d_in, d_out, d_X.shape[0])
+    if d_work is None or d_work.numel() * d_work.element_size() < ws:
+        raise ValueError(f"work holds fewer than the {ws} bytes mlp_backward needs")
     _check(lib().mlp_backward(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_T), _dev(d_M),
                               _dev(d_grad), _dev(d_loss), _dev(d_work), _stream(stream)), "mlp_backward")
 
 
 def mlp_adam_step(d_params, d_grad, d_m, d_v, step: int, lr: float = 1e-3, beta1: float = 0.9,
                   beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    n = d_params.numel()
+    for name, t in (("grad", d_grad), ("m", d_m), ("v", d_v)):
+        _dev_vec(t, n, PJDS_F32, name, like=d_params)
     _check(lib().mlp_adam_step(_dev(d_params), _dev(d_grad), _dev(d_m), _dev(d_v), d_params.numel(), step,
                                lr, beta1, beta2, eps, _stream(stream)), "mlp_adam_step")
 
 
 def mlp_infer(d_params, d_in: int, d_out: int, d_X, d_scale, d_shift, d_valid, d_idx, d_margin, stream=None) -> None:
+    _mlp_operands(d_params, d_in, d_out, d_X, {"idx": (d_idx, 1, None), "margin": (d_margin, 1, PJDS_F32)})
+    for name, t in (("scale", d_scale), ("shift", d_shift), ("valid", d_valid)):
+        _dev_vec(t, d_out, PJDS_F32, name, like=d_params, required=False)
+    _dev_int(d_idx, d_X.shape[0], np.int32, "idx")
     _check(lib().mlp_infer(_dev(d_params), d_in, d_out, d_X.shape[0], _dev(d_X), _dev(d_scale), _dev(d_shift),
                            _dev(d_valid), _dev(d_idx), _dev(d_margin), _stream(stream)), "mlp_infer")
 
 
 def pjds_spmv_axpby(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work,
                     d_x, alpha: float, beta: float, d_z, d_y, flags: int = 0, stream=None) -> None:
+    code = _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
+                          need_perm=not flags & PJDS_Y_PERMUTED)
+    _dev_vec(d_z, info.n_rows, code, "z", like=d_y, required=False)
+    _dev_int(d_sched, 4 * info.n_chunks, np.int32, "sched", like=d_y, required=info.n_chunks > 0)
     _check(lib().pjds_spmv_axpby(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                                  _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
                                  _dtype_code(d_y.dtype), _dev(d_x), alpha, beta, _dev(d_z), _dev(d_y),
@@ -378,6 +528,13 @@ def pjds_lanczos_workspace(info: pjds_info) -> tuple[int, int]:
 def pjds_lanczos(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, d_v0,
                  steps: int, x_halo: int, tile_rows: int, d_alpha, d_beta, d_vectors, d_scratch,
                  stream=None) -> None:
+    if steps > 0 and info.n_rows > 0:
+        _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, None, d_v0, d_v0, need_perm=False)
+        _dev_vec(d_alpha, steps, PJDS_F64, "alpha", like=d_v0)
+        _dev_vec(d_beta, steps + 1, PJDS_F64, "beta", like=d_v0)
+        vb, sb = pjds_lanczos_workspace(info)
+        _dev_vec(d_vectors, vb // 8, PJDS_F64, "vectors", like=d_v0)
+        _dev_vec(d_scratch, sb // 8, PJDS_F64, "scratch", like=d_v0)
     _check(lib().pjds_lanczos(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                               _dev(d_val_p), _dev(d_sched), _dev(d_work), _dev(d_v0), steps, x_halo,
                               tile_rows, _dev(d_alpha), _dev(d_beta), _dev(d_vectors), _dev(d_scratch),

@@ -414,6 +414,8 @@ int create(int32_t n_members, const pjds_batch_member *members, int32_t dtype, u
             return fail(PJDS_ERR_ARG, "member %d: NULL device array", k);
         if (in.nnz_stored && (!m.d_col_p || !m.d_val_p || !m.d_x))
             return fail(PJDS_ERR_ARG, "member %d: NULL device array", k);
+        // the staged kernel copies each tile's range of x into LDS, even without entries
+        if (staged && in.n_rows && in.n_cols && !m.d_x) return fail(PJDS_ERR_ARG, "member %d: d_x is NULL", k);
         if (in.n_rows && !(flags & PJDS_Y_PERMUTED) && !m.d_perm)
             return fail(PJDS_ERR_ARG, "member %d: d_perm is NULL (needed to scatter y)", k);
         if (ceil_div(in.n_pad, kWave) > INT32_MAX) return fail(PJDS_ERR_OVERFLOW, "member %d too large", k);

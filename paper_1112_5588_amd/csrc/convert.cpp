@@ -311,6 +311,11 @@ int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
                              in.split_len == 0 ? -1 : in.split_len, window, split))
         return rc;
     if (row_ptr[in.n_rows] != in.nnz) return fail(PJDS_ERR_ARG, "info does not match row_ptr (nnz %lld vs %lld)", (long long)in.nnz, (long long)row_ptr[in.n_rows]);
+    // every size the caller sized its buffers by must be the planner's own, before anything is
+    // allocated from it or written
+    if (in.n_pad != ceil_div(in.n_rows, in.block_height) * in.block_height || in.n_blocks != in.n_pad / in.block_height ||
+        in.sort_window != window || in.split_len != split)
+        return fail(PJDS_ERR_ARG, "info does not match the planner's sizes (re-run pjds_plan)");
     if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
     if ((in.n_rows && !perm) || !row_len || !offsets) return fail(PJDS_ERR_ARG, "NULL output array");
     if (in.nnz_stored && (!col_p || !val_p)) return fail(PJDS_ERR_ARG, "NULL output array");
@@ -329,7 +334,9 @@ int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
     sort_rows(in.n_rows, in.n_pad, window, row_ptr, tperm.data(), tlen.data());
     Plan p;
     size_blocks(in.n_pad, in.block_height, lanes_per_row(in.flags), in.split_len, tlen.data(), p);
-    if (p.nnz_stored != in.nnz_stored || p.n_chunks != in.n_chunks)
+    const int64_t n_offsets = (in.flags & PJDS_LAYOUT_BLOCK) ? p.n_blocks + 1 : int64_t(p.max_len) + 1;
+    if (p.nnz_stored != in.nnz_stored || p.n_chunks != in.n_chunks || p.n_split != in.n_split_groups ||
+        p.max_len != in.max_row_len || n_offsets != in.n_offsets)
         return fail(PJDS_ERR_ARG, "info does not match the matrix (re-run pjds_plan)");
 
     std::vector<int32_t> invperm;
@@ -417,6 +424,10 @@ int ellr_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
     if (!rowmax || (in.nnz_stored && (!col_e || !val_e)) || (in.nnz && !val))
         return fail(PJDS_ERR_ARG, "NULL array");
     if (int rc = check_columns(in.nnz, in.n_cols, col_idx)) return rc;
+    int64_t mx = 0;
+    for (int64_t i = 0; i < in.n_rows; ++i) mx = std::max(mx, row_ptr[i + 1] - row_ptr[i]);
+    if (in.max_row_len != mx || in.nnz_stored != in.n_pad * mx)
+        return fail(PJDS_ERR_ARG, "info does not match the matrix (re-run ellr_plan)");
     const int64_t n = in.n_rows, np = in.n_pad, L = in.max_row_len;
     auto fill = [&](auto *dst, const auto *src) {
         using T = std::remove_pointer_t<decltype(dst)>;

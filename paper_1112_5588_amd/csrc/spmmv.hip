@@ -171,7 +171,9 @@ extern "C" int pjds_spmmv_xlds(const pjds_info *info, const int32_t *d_row_len, 
     if (ceil_div(k, t) > 65535 || ceil_div(info->n_pad, tile) > INT32_MAX) return fail(PJDS_ERR_ARG, "grid too large");
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_Y) return fail(PJDS_ERR_ARG, "NULL device array");
-    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_X)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p)) return fail(PJDS_ERR_ARG, "NULL device array");
+    // every tile copies its rows of X into LDS, even when the matrix has no entries
+    if (info->n_cols && !d_X) return fail(PJDS_ERR_ARG, "d_X is NULL");
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter Y)");
     const int64_t elt = dtype == PJDS_F64 ? 8 : 4;
     if ((reinterpret_cast<uintptr_t>(d_X) | reinterpret_cast<uintptr_t>(d_Y)) % uintptr_t(elt * vpl))

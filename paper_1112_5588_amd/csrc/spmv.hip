@@ -980,7 +980,9 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
     if (int rc = pjds::check_xlds(*info, dtype, x_halo, tile_rows)) return rc;
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
-    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p)) return fail(PJDS_ERR_ARG, "NULL device array");
+    // every tile copies its range of x into LDS, even when the matrix has no entries
+    if (info->n_cols && !d_x) return fail(PJDS_ERR_ARG, "d_x is NULL");
     if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
     pjds::launch_xlds(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, dtype, d_x, d_y, x_halo, tile_rows,
                       EpiArgs{}, flags, static_cast<hipStream_t>(stream));

@@ -246,7 +246,7 @@ class CsrMatrix:
     def spmv(self, x, y=None, variant: int = 1, stream=None):
         if y is None:
             y = torch.empty(self.n_rows, dtype=self.dtype, device=self.device)
-        L.csr_spmv(self.n_rows, self.n_cols, self.row_ptr, self.col, self.val, x, y, variant, stream)
+        L.csr_spmv(self.n_rows, self.n_cols, self.row_ptr, self.col, self.val, x, y, variant, stream, nnz=self.nnz)
         return y
 
     def footprint_bytes(self) -> int:

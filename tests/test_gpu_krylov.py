@@ -10,6 +10,7 @@ import synth
 from oracle import krylov
 from paper_1112_5588_amd import PjdsMatrix
 from paper_1112_5588_amd.matrix import split_columns
+from parity import assert_rows, assert_rows_axpby
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +44,8 @@ def test_axpby_matches_oracle(y_permuted, alias, dtype):
     if y_permuted:
         ref = ref[perm]
     assert oracle.rel_l2(host(y), ref) <= (1e-12 if dtype == np.float64 else 1e-5)
+    assert_rows_axpby(host(y), A, x, -1.5, 0.25, z, 8 if dtype == np.float64 else 4,
+                      rows=perm if y_permuted else None)
 
 
 def test_axpby_long_row_work_items_and_identity():
@@ -54,6 +57,7 @@ def test_axpby_long_row_work_items_and_identity():
     y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
     M.spmv_axpby(dev(x), y, alpha=2.0, beta=-1.0, z=dev(z))
     assert oracle.rel_l2(host(y), krylov.axpby(A, x, 2.0, -1.0, z)) <= 1e-12
+    assert_rows_axpby(host(y), A, x, 2.0, -1.0, z)
     # alpha = 1 without z is the plain product, bit for bit
     M.spmv_axpby(dev(x), y)
     assert torch.equal(y, M.spmv(dev(x)))
@@ -70,7 +74,8 @@ def test_local_nonlocal_split_adds_up_to_the_product():
     xd = dev(x)
     y = ML.spmv(xd)
     MN.spmv_axpby(xd, y, alpha=1.0, beta=1.0, z=y)
-    assert oracle.rel_l2(host(y), oracle.csr_spmv(A, x)) <= 1e-12
+    # the two parts' sums added once more: one extra rounded term per row
+    assert_rows(host(y), A, x, extra_terms=1)
 
 
 @pytest.mark.parametrize("path", ["plain", "lds"])

@@ -9,6 +9,7 @@ import oracle
 import synth
 from oracle import krylov
 from paper_1112_5588_amd import PjdsMatrix
+from parity import assert_rows, assert_rows_axpby
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +32,8 @@ def run(A, x, lanes, window=0, y_permuted=False, symmetric=False):
     perm = M.host["perm"]
     y = host(M.spmv(dev(x[perm] if symmetric else x, M.dtype), y_permuted=y_permuted))
     ref = oracle.csr_spmv(A, x)
+    # every row against its own error bound (the T partial sums are added in a tree)
+    assert_rows(y, A, x, 8 if M.dtype == torch.float64 else 4, rows=perm if y_permuted else None)
     return M, y, (ref[perm] if y_permuted else ref)
 
 
@@ -73,6 +76,7 @@ def test_symmetric_basis_and_fused_update():
     yz = dev(z[perm])
     M.spmv_axpby(dev(x[perm]), yz, alpha=0.5, beta=-2.0, z=yz, y_permuted=True)
     assert oracle.rel_l2(host(yz), krylov.axpby(A, x, 0.5, -2.0, z)[perm]) <= 1e-12
+    assert_rows_axpby(host(yz), A, x, 0.5, -2.0, z, rows=perm)
 
 
 def test_lanczos_plain_path_takes_lanes():
@@ -115,9 +119,5 @@ def test_powerlaw_full_size_sampled():
     y = host(M.spmv(dev(x)))
     rows = np.unique(np.concatenate([M.host["perm"][:2048],
                                      (synth.uniform01(79, 1, 4096) * A.n_rows).astype(np.int64)]))
-    lens = np.diff(A.row_ptr)[rows]
-    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
-    idx = np.concatenate([np.arange(A.row_ptr[r], A.row_ptr[r + 1]) for r in rows])
-    ref = oracle.csr_spmv(synth.CSR(len(rows), A.n_cols, rp, A.col[idx], A.val[idx]), x)
-    assert oracle.rel_l2(y[rows], ref) <= 1e-12
+    assert_rows(y[rows], A, x, rows=rows)
     assert np.array_equal(host(M.spmv(dev(x))), y)

@@ -9,6 +9,7 @@ import oracle
 import synth
 from paper_1112_5588_amd import CsrMatrix, EllrMatrix, PjdsMatrix
 from paper_1112_5588_amd import _lib as L
+from parity import assert_rows, assert_rows_mm
 
 pytestmark = pytest.mark.gpu
 
@@ -33,11 +34,9 @@ def check_pjds(A, x, b_r=64, layout="jd", window=0, y_permuted=False, symmetric=
     y = host(M.spmv(dev(xin, M.dtype), y_permuted=y_permuted))
     # symmetric renumbering changes the basis of x only: slot i of the product is still
     # original row perm[i], written there (y_permuted) or scattered back to row perm[i]
-    ref = oracle.csr_spmv(A, x)
-    if y_permuted:
-        ref = ref[perm]
-    err = oracle.rel_l2(y, ref)
-    assert err <= (tol if tol is not None else TOL[M.dtype]), err
+    vb = 8 if M.dtype == torch.float64 else 4
+    # slot i holds original row perm[i] when y is permuted
+    assert_rows(y, A, x, vb, rows=perm if y_permuted else None, tol=tol)
     return M, y
 
 
@@ -128,7 +127,7 @@ def test_padding_never_enters_the_sum():
         assert M.info.nnz_stored > A.nnz
         y = host(M.spmv(dev(x)))
         assert np.all(np.isfinite(y))
-        assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-12
+        assert_rows(y, A, x)
 
 
 def test_empty_inputs():
@@ -152,7 +151,7 @@ def test_ellr_parity(dtype):
             x = x.astype(np.float32).astype(np.float64)
         E = EllrMatrix.from_csr(A)
         y = host(E.spmv(dev(x, E.dtype)))
-        assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= TOL[E.dtype]
+        assert_rows(y, A, x, 8 if E.dtype == torch.float64 else 4)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -164,7 +163,7 @@ def test_csr_parity(dtype, variant):
         x = x.astype(np.float32).astype(np.float64)
     C = CsrMatrix.from_csr(A)
     y1 = host(C.spmv(dev(x, C.dtype), variant=variant))
-    assert oracle.rel_l2(y1, oracle.csr_spmv(A, x)) <= TOL[C.dtype]
+    assert_rows(y1, A, x, 8 if C.dtype == torch.float64 else 4)
     assert np.array_equal(host(C.spmv(dev(x, C.dtype), variant=variant)), y1)
 
 
@@ -180,8 +179,7 @@ def test_spmmv_config1(k, t, vpl):
     X = synth.dense_x(A.n_cols, 40, k=k).reshape(A.n_cols, k)
     M = PjdsMatrix.from_csr(A)
     Y = host(M.spmmv(dev(X), vectors_per_tile=t, vectors_per_lane=vpl))
-    ref = oracle.csr_spmmv(A, X)
-    assert oracle.rel_l2(Y, ref) <= 1e-12
+    assert_rows_mm(Y, A, X)
     if k == 1:
         assert np.array_equal(Y[:, 0], host(M.spmv(dev(X[:, 0]))))
 
@@ -193,9 +191,9 @@ def test_spmmv_wide_lanes_ragged_tiles(b_r, layout, k, t, vpl):
     X = synth.dense_x(7000, 43, k=k).reshape(7000, k)
     M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, sort_window=1024 if layout == "block" else 0)
     Y = host(M.spmmv(dev(X), vectors_per_tile=t, vectors_per_lane=vpl))
-    assert oracle.rel_l2(Y, oracle.csr_spmmv(A, X)) <= 1e-12
+    assert_rows_mm(Y, A, X)
     Y32 = host(PjdsMatrix.from_csr(A.astype(np.float32)).spmmv(dev(X, torch.float32), vectors_per_tile=t, vectors_per_lane=vpl))
-    assert oracle.rel_l2(Y32, oracle.csr_spmmv(A.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))) <= 1e-5
+    assert_rows_mm(Y32, A.astype(np.float32), X.astype(np.float32).astype(np.float64), value_bytes=4)
 
 
 def test_spmmv_rejects_misaligned_lanes():
@@ -212,10 +210,7 @@ def test_spmmv_random(b_r, layout):
     M = PjdsMatrix.from_csr(A, block_height=b_r, layout=layout, keep_host=True)
     for yp in (False, True):
         Y = host(M.spmmv(dev(X), vectors_per_tile=4, vectors_per_lane=1, y_permuted=yp))
-        ref = oracle.csr_spmmv(A, X)
-        if yp:
-            ref = ref[M.host["perm"]]
-        assert oracle.rel_l2(Y, ref) <= 1e-12
+        assert_rows_mm(Y, A, X, rows=M.host["perm"] if yp else None)
 
 
 @pytest.mark.parametrize("window", [256, 4096])
@@ -227,8 +222,7 @@ def test_spmmv_xcd_renumbering_is_bitwise_identical(window):
     Y0 = M.spmmv(X, vectors_per_tile=8, vectors_per_lane=4, y_permuted=True)
     Y1 = M.spmmv(X, vectors_per_tile=8, vectors_per_lane=4, y_permuted=True, xcd_remap=True)
     assert torch.equal(Y0, Y1)
-    ref = oracle.csr_spmmv(A, host(X))[M.host["perm"]]
-    assert oracle.rel_l2(host(Y1), ref) <= 1e-12
+    assert_rows_mm(host(Y1), A, host(X), rows=M.host["perm"])
 
 
 # ------------------------------------------------------------------ SpMMV with X staged in LDS
@@ -247,8 +241,7 @@ def test_spmmv_xlds_equals_spmmv_bitwise(k, t, vpl, window, halo, tile):
         Y0 = M.spmmv(X, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=yp)
         Y1 = M.spmmv_xlds(X, vectors_per_tile=t, vectors_per_lane=vpl, x_halo=halo, tile_rows=tile, y_permuted=yp)
         assert torch.equal(Y0, Y1)
-    ref = oracle.csr_spmmv(A, host(X))[M.host["perm"]]
-    assert oracle.rel_l2(host(Y1), ref) <= 1e-12
+    assert_rows_mm(host(Y1), A, host(X), rows=M.host["perm"])
 
 
 @pytest.mark.parametrize("k,t", [(4, 4), (8, 8)])
@@ -262,7 +255,7 @@ def test_spmmv_xlds_xcd_groups_with_a_tail(k, t):
     Y = torch.full((A.n_rows, k), float("nan"), dtype=torch.float64, device="cuda")
     M.spmmv_xlds(X, Y, vectors_per_tile=t, vectors_per_lane=4, x_halo=512, tile_rows=256)
     assert torch.equal(Y, M.spmmv(X, vectors_per_tile=t, vectors_per_lane=4))
-    assert oracle.rel_l2(host(Y), oracle.csr_spmmv(A, host(X))) <= 1e-12
+    assert_rows_mm(host(Y), A, host(X))
 
 
 @pytest.mark.parametrize("b_r", [32, 128])
@@ -274,8 +267,7 @@ def test_spmmv_xlds_block_heights_float32_and_small(b_r):
         Y0 = M.spmmv(dev(X, torch.float32), vectors_per_tile=4, vectors_per_lane=4)
         Y1 = M.spmmv_xlds(dev(X, torch.float32), vectors_per_tile=4, vectors_per_lane=4, x_halo=256, tile_rows=256)
         assert torch.equal(Y0, Y1)
-        ref = oracle.csr_spmmv(A.astype(np.float64), X.astype(np.float64))
-        assert oracle.rel_l2(host(Y1), ref) <= 1e-5
+        assert_rows_mm(host(Y1), A, X.astype(np.float64), value_bytes=4)
 
 
 def test_spmmv_xlds_refusals():
@@ -320,8 +312,7 @@ def test_hh_like_full_size_sampled(hh_full, dtype):
     # permuted slot i holds original row perm[i]
     inv = np.empty_like(M.host["perm"])
     inv[M.host["perm"]] = np.arange(A.n_rows, dtype=np.int32)
-    ref = oracle.csr_spmv(sampled_rows(A, rows), x)
-    assert oracle.rel_l2(y[inv[rows]], ref) <= TOL[M.dtype]
+    assert_rows(y[inv[rows]], A, x, 8 if M.dtype == torch.float64 else 4, rows=rows)
     # footprint: pJDS stores fewer entries than ELLPACK-R would
     E_info = EllrMatrix.plan(A)
     assert M.info.nnz_stored < E_info.nnz_stored
@@ -345,7 +336,7 @@ def test_headline_configuration_full_size(hh_full, dtype):
                                      (synth.uniform01(81, 1, 4096) * A.n_rows).astype(np.int64)]))
     inv = np.empty_like(M.host["perm"])
     inv[M.host["perm"]] = np.arange(A.n_rows, dtype=np.int32)
-    assert oracle.rel_l2(y[inv[rows]], oracle.csr_spmv(sampled_rows(A, rows), x)) <= TOL[M.dtype]
+    assert_rows(y[inv[rows]], A, x, 8 if M.dtype == torch.float64 else 4, rows=rows)
     assert torch.equal(yd, M.spmv(xd, y_permuted=True))
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=512, tile_rows=512, y_permuted=True))
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True))
@@ -364,8 +355,7 @@ def test_spmmv_xlds_full_size(hh_full, k, t, tile):
     perm = M.host["perm"]
     rows_p = np.unique(np.concatenate([np.arange(256), np.arange(A.n_rows - 256, A.n_rows),
                                        (synth.uniform01(82, 1, 2048) * A.n_rows).astype(np.int64)]))
-    ref = oracle.csr_spmmv(sampled_rows(A, perm[rows_p]), X_np)
-    assert oracle.rel_l2(host(Y)[rows_p], ref) <= 1e-12
+    assert_rows_mm(host(Y)[rows_p], A, X_np, rows=perm[rows_p])
 
 
 def test_powerlaw_full_size_sampled():
@@ -376,8 +366,7 @@ def test_powerlaw_full_size_sampled():
     y = host(M.spmv(dev(x)))
     rows = np.unique(np.concatenate([M.host["perm"][:2048],          # the longest rows (split)
                                      (synth.uniform01(78, 1, 4096) * A.n_rows).astype(np.int64)]))
-    ref = oracle.csr_spmv(sampled_rows(A, rows), x)
-    assert oracle.rel_l2(y[rows], ref) <= 1e-12
+    assert_rows(y[rows], A, x, rows=rows)
     assert np.array_equal(host(M.spmv(dev(x))), y)
 
 
@@ -394,10 +383,7 @@ def test_xlds_matches_oracle_and_plain_kernel(b_r, window, halo, tile, y_permute
     M = PjdsMatrix.from_csr(A, block_height=b_r, layout="block", sort_window=window, keep_host=True)
     xd = dev(x)
     y = host(M.spmv_xlds(xd, x_halo=halo, tile_rows=tile, y_permuted=y_permuted))
-    ref = oracle.csr_spmv(A, x)
-    if y_permuted:
-        ref = ref[M.host["perm"]]
-    assert oracle.rel_l2(y, ref) <= 1e-12
+    assert_rows(y, A, x, rows=M.host["perm"] if y_permuted else None)
     # the same values reach the same FMAs in the same order: bit-identical to the plain kernel
     assert np.array_equal(y, host(M.spmv(xd, y_permuted=y_permuted)))
     # two adjacent rows per lane: again the same FMAs in the same order
@@ -418,7 +404,7 @@ def test_xlds_two_rows_ragged_and_fused_update(dtype, n):
     xd = dev(x, M.dtype)
     for tile in (256, 512, 1024):
         y = M.spmv_xlds(xd, x_halo=256, tile_rows=tile, two_rows=True)
-        assert oracle.rel_l2(host(y), oracle.csr_spmv(A, x)) <= TOL[M.dtype]
+        assert_rows(host(y), A, x, 8 if M.dtype == torch.float64 else 4)
         assert torch.equal(y, M.spmv(xd))
 
 
@@ -427,7 +413,7 @@ def test_xlds_float32_rectangular_and_wide_rows():
     x = synth.dense_x(3000, 29).astype(np.float32).astype(np.float64)
     M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=1024)
     y = host(M.spmv_xlds(dev(x, torch.float32), x_halo=2048))
-    assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-5
+    assert_rows(y, A, x, 4)
 
 
 def test_xlds_rejects_unsupported_layouts():
@@ -455,7 +441,7 @@ def test_plain_two_rows_bitwise(b_r, layout, window, y_permuted):
     y2 = M.spmv(x, y_permuted=y_permuted, two_rows=True)
     assert torch.equal(y1, y2)
     if not y_permuted:
-        assert oracle.rel_l2(host(y2), oracle.csr_spmv(A, host(x))) <= 1e-12
+        assert_rows(host(y2), A, host(x))
 
 
 def test_plain_two_rows_float32_and_refusals():
@@ -463,7 +449,7 @@ def test_plain_two_rows_float32_and_refusals():
     x = synth.dense_x(A.n_cols, 45).astype(np.float32).astype(np.float64)
     M = PjdsMatrix.from_csr(A, layout="block", sort_window=256, split_len=-1)
     y = host(M.spmv(dev(x, torch.float32), two_rows=True))
-    assert oracle.rel_l2(y, oracle.csr_spmv(A, x)) <= 1e-5
+    assert_rows(y, A, x, 4)
     P = synth.powerlaw(1 << 14, seed=46, l_max=2000)
     with pytest.raises(L.PjdsError) as e:                   # long rows split into work items
         PjdsMatrix.from_csr(P, split_len=64).spmv(dev(synth.dense_x(P.n_cols, 46)), two_rows=True)

@@ -378,3 +378,20 @@ def test_ellr_layout_and_product(seed):
             y[i] += E["val"][j * E["n_pad"] + i] * x[E["col"][j * E["n_pad"] + i]]
     assert np.array_equal(y, dense(A) @ x)
     assert np.all(E["rowmax"][130:] == 0)
+
+
+def test_rel_l2_hand_computed():
+    # ||(3, 4) - (0, 0)|| / ||(0, 0)|| takes the absolute branch: 5
+    assert oracle.rel_l2(np.array([3.0, 4.0]), np.zeros(2)) == 5.0
+    # ||(1, 2, 2) - (0, 0, 0)|| / ... with y_ref = (2, 0, 0): d = (-1, 2, 2), ||d|| = 3, ||ref|| = 2
+    assert oracle.rel_l2(np.array([1.0, 2.0, 2.0]), np.array([2.0, 0.0, 0.0])) == 1.5
+    # the denominator is the reference's norm, not the candidate's: swapping the arguments
+    # gives 3 / 3
+    assert oracle.rel_l2(np.array([2.0, 0.0, 0.0]), np.array([1.0, 2.0, 2.0])) == 1.0
+    # equal vectors, and float32 input widened exactly
+    assert oracle.rel_l2(np.array([0.1, -7.0]), np.array([0.1, -7.0])) == 0.0
+    assert oracle.rel_l2(np.float32([0.5, 0.25]), np.array([0.5, 0.0])) == 0.5
+    # matrices are flattened: a difference [[0, 3], [4, 0]] of norm 5 against a reference
+    # of norm 10
+    assert oracle.rel_l2(np.array([[6.0, 3.0], [4.0, 8.0]]), np.array([[6.0, 0.0], [0.0, 8.0]])) == 0.5
+    assert oracle.rel_l2(np.zeros(0), np.zeros(0)) == 0.0

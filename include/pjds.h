@@ -323,6 +323,28 @@ int pjds_batch_info(const pjds_batch *batch, int32_t *n_tiles, int32_t *grid);
 /* Free the handle, its device tables and graph (synchronise first if launches may still run). */
 int pjds_batch_destroy(pjds_batch *batch);
 
+/* ---- local / non-local split (Sect. 3.1, vector mode) ------------------------------- */
+/*
+ * A row-distributed product splits its rows' entries by column: A = A_loc + A_nl, where A_loc
+ * holds the entries whose column lies in [c0, c1) (the columns of x the process owns) and
+ * A_nl the rest.  The local product can then start while the non-local x entries are still
+ * being exchanged, and the non-local product adds into y afterwards.  Both parts keep A's
+ * n_rows x n_cols shape and each row's entries in their stored order, so they convert and
+ * multiply like any CSR matrix (pjds_spmv for A_loc, pjds_spmv_axpby with b = 1, z = y for
+ * A_nl).  Host arrays only.
+ *
+ * pjds_split_count: *nnz_local = entries of A_loc (A_nl has nnz - *nnz_local).
+ * pjds_split_columns: writes rp_loc[n_rows+1], col_loc/val_loc[nnz_local] and
+ *   rp_nl[n_rows+1], col_nl/val_nl[nnz - nnz_local]; values of type dtype are copied bit for
+ *   bit.  0 <= c0 <= c1 <= n_cols, else ERR_ARG; row_ptr and columns are validated as by
+ *   pjds_plan and pjds_convert before anything is written.
+ */
+int pjds_split_count(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, const int32_t *col_idx,
+                     int64_t c0, int64_t c1, int64_t *nnz_local);
+int pjds_split_columns(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, const int32_t *col_idx,
+                       const void *val, int32_t dtype, int64_t c0, int64_t c1, int64_t *rp_loc,
+                       int32_t *col_loc, void *val_loc, int64_t *rp_nl, int32_t *col_nl, void *val_nl);
+
 /* ---- ELLPACK-R (Sect. 2.1, Listing 1) ---------------------------------------------- */
 /*
  * Rows keep their order; the non-zeros of each row are shifted left and the
@@ -394,8 +416,12 @@ int mlp_infer(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch,
               float *d_margin, void *stream);
 
 /* ---- measurement helpers ------------------------------------------------------------ */
-/* Stream probes for the achievable bandwidth ceiling: mode 0 reads n doubles and writes one
- * value per workgroup to d_out (reduction), mode 1 copies n doubles d_in -> d_out. */
+/* Stream probes for the achievable bandwidth ceiling, 16-byte loads with several in flight per
+ * thread.  mode 0 reads n doubles with non-temporal loads and writes one partial sum per
+ * workgroup to d_out (at most 2048 values), mode 1 copies n doubles d_in -> d_out, mode 2
+ * reads like mode 0 with ordinary cached loads: a read-only pass that evicts what the caches
+ * (the Infinity Cache included) held before, leaving no dirty line to write back.  d_in and
+ * d_out are device arrays of n doubles (mode 1) or of n and 2048 doubles (modes 0, 2). */
 int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream);
 
 /* ---- diagnostics ------------------------------------------------------------------- */

@@ -34,13 +34,23 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 _f32p = ctypes.POINTER(ctypes.c_float)
 
 
+_SO_T = os.path.join(_HERE, "liboracle_threads.so")
+_SRC_T = os.path.join(_HERE, "csr_threads.c")
+
+
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` with gcc: -O2, no FP contraction, generic x86-64 code."""
+    """Compile ``oracle.c`` with gcc: -O2, no FP contraction, generic x86-64 code; and the
+    all-core timing form ``csr_threads.c`` (-O3, OpenMP, no FP contraction)."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
                                "-fPIC", "-shared", _SRC, "-o", tmp])
         os.replace(tmp, _SO)
+    if force or not os.path.exists(_SO_T):
+        tmp = _SO_T + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-fPIC", "-shared", _SRC_T, "-o", tmp])
+        os.replace(tmp, _SO_T)
     return _SO
 
 
@@ -69,6 +79,38 @@ def lib() -> ctypes.CDLL:
                                        _f64p, _i32p, _i32p, _f64p]
         _lib = L
     return _lib
+
+
+_lib_t = None
+
+
+def lib_threads() -> ctypes.CDLL:
+    global _lib_t
+    if _lib_t is None:
+        if not os.path.exists(_SO_T):
+            build(force=False)
+        L = ctypes.CDLL(_SO_T)
+        L.oracle_csr_spmv_threads.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
+        L.oracle_csr_spmv_f32val_threads.argtypes = [ctypes.c_int64, _i64p, _i32p, _f32p, _f64p, _f64p]
+        _lib_t = L
+    return _lib_t
+
+
+def csr_spmv_threads(A, x: np.ndarray, y: np.ndarray | None = None) -> tuple[np.ndarray, int]:
+    """The same product as ``csr_spmv`` with the rows shared among all OpenMP threads (bitwise
+    the same result); for timing the CPU baseline on every core.  Returns (y, threads used)."""
+    rp, col = _c(A.row_ptr, np.int64), _c(A.col, np.int32)
+    x = _c(x, np.float64)
+    if y is None:
+        y = np.empty(A.n_rows, dtype=np.float64)
+    if A.val.dtype == np.float32:
+        used = lib_threads().oracle_csr_spmv_f32val_threads(A.n_rows, _p(rp, _i64p), _p(col, _i32p),
+                                                            _p(_c(A.val, np.float32), _f32p), _p(x, _f64p),
+                                                            _p(y, _f64p))
+    else:
+        used = lib_threads().oracle_csr_spmv_threads(A.n_rows, _p(rp, _i64p), _p(col, _i32p),
+                                                     _p(_c(A.val, np.float64), _f64p), _p(x, _f64p), _p(y, _f64p))
+    return y, int(used)
 
 
 def _p(a: np.ndarray, t):
@@ -202,3 +244,19 @@ def rel_l2(y: np.ndarray, y_ref: np.ndarray) -> float:
     d = float(np.linalg.norm(y - y_ref))
     r = float(np.linalg.norm(y_ref))
     return d / r if r > 0 else d
+
+
+def split_columns(A, c0: int, c1: int):
+    """The local/non-local split of Sect. 3.1 (vector mode), row by row from its definition:
+    entries with column in [c0, c1) go to the local part, the others to the non-local part,
+    each row keeping its order.  Returns ((row_ptr, col, val) local, (row_ptr, col, val) rest)."""
+    parts = ([0], [], []), ([0], [], [])
+    for i in range(A.n_rows):
+        for k in range(int(A.row_ptr[i]), int(A.row_ptr[i + 1])):
+            p = parts[0] if c0 <= int(A.col[k]) < c1 else parts[1]
+            p[1].append(int(A.col[k]))
+            p[2].append(A.val[k])
+        for p in parts:
+            p[0].append(len(p[1]))
+    return tuple((np.array(rp, np.int64), np.array(c, np.int32), np.array(v, dtype=np.asarray(A.val).dtype))
+                 for rp, c, v in parts)

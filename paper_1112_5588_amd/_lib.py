@@ -93,6 +93,8 @@ _SIGS = {
     "pjds_lanczos_workspace": [_ip, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
+    "pjds_split_count": [_i64, _i64, _vp, _vp, _i64, _i64, ctypes.POINTER(_i64)],
+    "pjds_split_columns": [_i64, _i64, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "ellr_plan": [_i64, _i64, _vp, _ip],
     "ellr_convert": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -335,6 +337,31 @@ def pjds_spmmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_p
                                  tile_rows, flags, _stream(stream)), "pjds_spmmv_xlds")
 
 
+def pjds_split_count(n_rows: int, n_cols: int, row_ptr, col_idx, c0: int, c1: int) -> int:
+    _host_arr(row_ptr, n_rows + 1, np.int64, "row_ptr")
+    out = _i64(0)
+    _check(lib().pjds_split_count(n_rows, n_cols, _host(row_ptr, np.int64), _host(col_idx, np.int32), c0, c1,
+                                  ctypes.byref(out)), "pjds_split_count")
+    return out.value
+
+
+def pjds_split_columns(n_rows: int, n_cols: int, row_ptr, col_idx, val, c0: int, c1: int,
+                       rp_loc, col_loc, val_loc, rp_nl, col_nl, val_nl) -> None:
+    _host_arr(row_ptr, n_rows + 1, np.int64, "row_ptr")
+    nnz = int(row_ptr[n_rows])
+    _host_arr(col_idx, nnz, np.int32, "col_idx")
+    _host_arr(val, nnz, None, "val")
+    loc = pjds_split_count(n_rows, n_cols, row_ptr, col_idx, c0, c1)
+    for name, a, n, dt in (("rp_loc", rp_loc, n_rows + 1, np.int64), ("rp_nl", rp_nl, n_rows + 1, np.int64),
+                           ("col_loc", col_loc, loc, np.int32), ("col_nl", col_nl, nnz - loc, np.int32),
+                           ("val_loc", val_loc, loc, val.dtype), ("val_nl", val_nl, nnz - loc, val.dtype)):
+        _host_arr(a, n, dt, name)
+    _check(lib().pjds_split_columns(n_rows, n_cols, _host(row_ptr, np.int64), _host(col_idx, np.int32), _host(val),
+                                    _dtype_code(val.dtype), c0, c1, _host(rp_loc, np.int64), _host(col_loc, np.int32),
+                                    _host(val_loc), _host(rp_nl, np.int64), _host(col_nl, np.int32), _host(val_nl)),
+           "pjds_split_columns")
+
+
 def ellr_plan(n_rows: int, n_cols: int, row_ptr: np.ndarray) -> pjds_info:
     info = pjds_info()
     _check(lib().ellr_plan(n_rows, n_cols, _host(row_ptr, np.int64), ctypes.byref(info)), "ellr_plan")
@@ -385,7 +412,7 @@ def csr_spmv(n_rows: int, n_cols: int, d_row_ptr, d_col, d_val, d_x, d_y, varian
 
 def pjds_probe(mode: int, d_in, d_out, n: int, stream=None) -> None:
     _dev_vec(d_in, n, PJDS_F64, "in")
-    _dev_vec(d_out, n if mode == 1 else 4096, PJDS_F64, "out", like=d_in)
+    _dev_vec(d_out, n if mode == 1 else 2048, PJDS_F64, "out", like=d_in)
     _check(lib().pjds_probe(mode, _dev(d_in), _dev(d_out), n, _stream(stream)), "pjds_probe")
 
 

@@ -390,6 +390,53 @@ int pjds_convert(const pjds_info *info, const int64_t *row_ptr, const int32_t *c
     return PJDS_OK;
 }
 
+int pjds_split_count(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, const int32_t *col_idx,
+                     int64_t c0, int64_t c1, int64_t *nnz_local) {
+    if (!nnz_local) return fail(PJDS_ERR_ARG, "nnz_local is NULL");
+    if (int rc = check_row_ptr(n_rows, n_cols, row_ptr)) return rc;
+    if (c0 < 0 || c1 < c0 || c1 > n_cols) return fail(PJDS_ERR_ARG, "column range [%lld, %lld) outside [0, %lld]",
+                                                     (long long)c0, (long long)c1, (long long)n_cols);
+    const int64_t nnz = row_ptr[n_rows];
+    if (int rc = check_columns(nnz, n_cols, col_idx)) return rc;
+    int64_t loc = 0;
+    for (int64_t k = 0; k < nnz; ++k) loc += col_idx[k] >= c0 && col_idx[k] < c1;
+    *nnz_local = loc;
+    return PJDS_OK;
+}
+
+int pjds_split_columns(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, const int32_t *col_idx,
+                       const void *val, int32_t dtype, int64_t c0, int64_t c1, int64_t *rp_loc,
+                       int32_t *col_loc, void *val_loc, int64_t *rp_nl, int32_t *col_nl, void *val_nl) {
+    int64_t loc = 0;
+    if (int rc = pjds_split_count(n_rows, n_cols, row_ptr, col_idx, c0, c1, &loc)) return rc;
+    if (dtype != PJDS_F64 && dtype != PJDS_F32) return fail(PJDS_ERR_ARG, "dtype %d", dtype);
+    const int64_t nnz = row_ptr[n_rows];
+    if (!rp_loc || !rp_nl) return fail(PJDS_ERR_ARG, "NULL row pointer output");
+    if ((loc && (!col_loc || !val_loc)) || (nnz - loc && (!col_nl || !val_nl)) || (nnz && !val))
+        return fail(PJDS_ERR_ARG, "NULL array");
+    const size_t esz = dtype == PJDS_F64 ? 8 : 4;
+    const char *v = static_cast<const char *>(val);
+    char *vl = static_cast<char *>(val_loc), *vn = static_cast<char *>(val_nl);
+    int64_t a = 0, b = 0;
+    rp_loc[0] = rp_nl[0] = 0;
+    for (int64_t i = 0; i < n_rows; ++i) {
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            if (col_idx[k] >= c0 && col_idx[k] < c1) {
+                col_loc[a] = col_idx[k];
+                std::memcpy(vl + size_t(a) * esz, v + size_t(k) * esz, esz);
+                ++a;
+            } else {
+                col_nl[b] = col_idx[k];
+                std::memcpy(vn + size_t(b) * esz, v + size_t(k) * esz, esz);
+                ++b;
+            }
+        }
+        rp_loc[i + 1] = a;
+        rp_nl[i + 1] = b;
+    }
+    return PJDS_OK;
+}
+
 int ellr_plan(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr, pjds_info *out) {
     if (!out) return fail(PJDS_ERR_ARG, "out is NULL");
     if (int rc = check_row_ptr(n_rows, n_cols, row_ptr)) return rc;

@@ -598,16 +598,32 @@ __global__ __launch_bounds__(kBlock) void csr_vector_kernel(
 }
 
 // ---- bandwidth probes ---------------------------------------------------------------------
+// Streams of 16-byte loads, kProbeInFlight independent ones per thread and iteration, over a
+// grid of kProbeBlocks workgroups (8 per CU): enough requests in flight to find the ceiling
+// the memory system gives a streaming kernel.
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+constexpr int kProbeInFlight = 4;
+constexpr int kProbeBlocks = 2048;
 
+// Sum of n doubles, one partial sum per workgroup in out[blockIdx.x].  NT: non-temporal loads
+// (the read ceiling); else ordinary loads that allocate in every cache level on the way (a pass
+// that evicts what the caches held and leaves no dirty line behind).
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void probe_read_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
-    double s = 0.0;
-    const int64_t n2 = n / 2;
+    const int64_t n2 = n / 2, stride = int64_t(gridDim.x) * kBlock;
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
-    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += int64_t(gridDim.x) * kBlock) {
-        dbl2 v = __builtin_nontemporal_load(in2 + k);
-        s += v.x + v.y;
+    dbl2 acc = {0.0, 0.0};
+    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += stride * kProbeInFlight) {
+        dbl2 v[kProbeInFlight];
+#pragma unroll
+        for (int u = 0; u < kProbeInFlight; ++u) {
+            const int64_t e = k + u * stride;
+            v[u] = e < n2 ? (NT ? __builtin_nontemporal_load(in2 + e) : in2[e]) : dbl2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeInFlight; ++u) acc += v[u];
     }
+    double s = acc.x + acc.y;
     if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) s += in[n - 1];
     __shared__ double red[kBlock];
     red[threadIdx.x] = s;
@@ -620,11 +636,22 @@ __global__ __launch_bounds__(kBlock) void probe_read_kernel(const double *__rest
 }
 
 __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
-    const int64_t n2 = n / 2;
+    const int64_t n2 = n / 2, stride = int64_t(gridDim.x) * kBlock;
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
     dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
-    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += int64_t(gridDim.x) * kBlock)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(in2 + k), out2 + k);
+    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += stride * kProbeInFlight) {
+        dbl2 v[kProbeInFlight];
+#pragma unroll
+        for (int u = 0; u < kProbeInFlight; ++u) {
+            const int64_t e = k + u * stride;
+            v[u] = e < n2 ? __builtin_nontemporal_load(in2 + e) : dbl2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeInFlight; ++u) {
+            const int64_t e = k + u * stride;
+            if (e < n2) __builtin_nontemporal_store(v[u], out2 + e);
+        }
+    }
     if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) out[n - 1] = in[n - 1];
 }
 
@@ -1036,10 +1063,11 @@ int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int
 }
 
 int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream) {
-    if ((mode != 0 && mode != 1) || n < 0 || !d_in || !d_out) return fail(PJDS_ERR_ARG, "bad probe arguments");
+    if ((mode != 0 && mode != 1 && mode != 2) || n < 0 || !d_in || !d_out) return fail(PJDS_ERR_ARG, "bad probe arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid(unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n / 2, kBlock * 8), 1), 256 * 16)));
-    if (mode == 0) hipLaunchKernelGGL(probe_read_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    const dim3 grid(unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n / 2, kBlock * kProbeInFlight), 1), kProbeBlocks)));
+    if (mode == 0) hipLaunchKernelGGL(probe_read_kernel<true>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    else if (mode == 2) hipLaunchKernelGGL(probe_read_kernel<false>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
     else hipLaunchKernelGGL(probe_copy_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
     return launch_status("pjds_probe");
 }

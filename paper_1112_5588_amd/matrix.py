@@ -296,21 +296,23 @@ class PjdsBatch:
 
 def split_columns(A, c0: int, c1: int):
     """A = A_local + A_nonlocal with A_local holding the entries whose column lies in [c0, c1)
-    (the local/non-local split of a row-distributed product); both keep A's row count and the
-    entries' order.  Returns two objects with n_rows, n_cols, row_ptr, col, val."""
+    (the local/non-local split of a row-distributed product, pjds_split_columns); both keep A's
+    row count and the entries' order.  Returns two objects with n_rows, n_cols, row_ptr, col, val."""
     class _Part:
         pass
-    rp = np.asarray(A.row_ptr, np.int64)
-    col = np.asarray(A.col)
-    val = np.asarray(A.val)
-    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(rp))
-    out = []
-    for keep in ((col >= c0) & (col < c1), ~((col >= c0) & (col < c1))):
+    rp = np.ascontiguousarray(A.row_ptr, np.int64)
+    col = np.ascontiguousarray(A.col, np.int32)
+    val = np.ascontiguousarray(A.val)
+    loc = L.pjds_split_count(A.n_rows, A.n_cols, rp, col, c0, c1)
+    nl = int(rp[A.n_rows]) - loc
+    parts = []
+    for n in (loc, nl):
         P = _Part()
         P.n_rows, P.n_cols = A.n_rows, A.n_cols
-        counts = np.bincount(rows[keep], minlength=A.n_rows)
-        P.row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
-        P.col = np.ascontiguousarray(col[keep], dtype=np.int32)
-        P.val = np.ascontiguousarray(val[keep])
-        out.append(P)
-    return out[0], out[1]
+        P.row_ptr = np.empty(A.n_rows + 1, np.int64)
+        P.col = np.empty(n, np.int32)
+        P.val = np.empty(n, val.dtype)
+        parts.append(P)
+    L.pjds_split_columns(A.n_rows, A.n_cols, rp, col, val, c0, c1, parts[0].row_ptr, parts[0].col, parts[0].val,
+                         parts[1].row_ptr, parts[1].col, parts[1].val)
+    return parts[0], parts[1]

@@ -161,3 +161,35 @@ def test_lanes_symmetric_float32_ragged(lanes):
     A = synth.hh_like(5001, seed=22)
     assert_same(A, b_r=64 // lanes, layout="block", symmetric=True, lanes=lanes)
     assert_same(A.astype(np.float32), b_r=64 // lanes, window=128, layout="block", lanes=lanes)
+
+
+@pytest.mark.parametrize("c0,c1", [(0, 0), (0, 3000), (700, 1900), (2999, 3000), (1200, 1200)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_split_columns_matches_oracle(c0, c1, dtype):
+    # the library's local/non-local split against the oracle's row-by-row definition: every
+    # array bit for bit, and the two parts together hold every entry exactly once
+    from paper_1112_5588_amd.matrix import split_columns
+    A = synth.random_csr(2001, 3000, 61, max_len=25, empty_frac=0.1).astype(dtype)
+    loc, nl = split_columns(A, c0, c1)
+    (rl, cl, vl), (rn, cn, vn) = oracle.split_columns(A, c0, c1)
+    for got, ref in ((loc.row_ptr, rl), (loc.col, cl), (nl.row_ptr, rn), (nl.col, cn)):
+        assert np.array_equal(got, ref)
+    assert np.array_equal(loc.val.view(np.uint8), vl.view(np.uint8))
+    assert np.array_equal(nl.val.view(np.uint8), vn.view(np.uint8))
+    assert rl[-1] + rn[-1] == A.nnz
+    assert np.all((cl >= c0) & (cl < c1)) and not np.any((cn >= c0) & (cn < c1))
+
+
+def test_split_columns_refusals():
+    A = synth.random_csr(50, 40, 62, max_len=5)
+    rp = np.ascontiguousarray(A.row_ptr, np.int64)
+    col = np.ascontiguousarray(A.col, np.int32)
+    for c0, c1 in ((-1, 10), (10, 5), (0, 41)):
+        with pytest.raises(L.PjdsError) as e:
+            L.pjds_split_count(A.n_rows, A.n_cols, rp, col, c0, c1)
+        assert e.value.code == L.PJDS_ERR_ARG
+    bad = col.copy()
+    bad[3] = 40
+    with pytest.raises(L.PjdsError) as e:
+        L.pjds_split_count(A.n_rows, A.n_cols, rp, bad, 0, 10)
+    assert e.value.code == L.PJDS_ERR_INDEX

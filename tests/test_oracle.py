@@ -395,3 +395,33 @@ def test_rel_l2_hand_computed():
     # of norm 10
     assert oracle.rel_l2(np.array([[6.0, 3.0], [4.0, 8.0]]), np.array([[6.0, 0.0], [0.0, 8.0]])) == 0.5
     assert oracle.rel_l2(np.zeros(0), np.zeros(0)) == 0.0
+
+
+@pytest.mark.parametrize("c0,c1", [(0, 29), (5, 17), (0, 0), (28, 29)])
+def test_split_columns_pinned_by_dense_brute_force(c0, c1):
+    # the two parts of the column split, as dense matrices: they add up to A, the local part
+    # lives in columns [c0, c1) only, the other part outside them; every row keeps its order
+    A = synth.random_csr(37, 29, 7, max_len=9, integer=True)
+    (rl, cl, vl), (rn, cn, vn) = oracle.split_columns(A, c0, c1)
+    L_ = synth.CSR(37, 29, rl, cl, vl)
+    N_ = synth.CSR(37, 29, rn, cn, vn)
+    DL, DN, DA = dense(L_), dense(N_), dense(A)
+    assert np.array_equal(DL + DN, DA)
+    inside = np.zeros(29, bool)
+    inside[c0:c1] = True
+    assert not DL[:, ~inside].any() and not DN[:, inside].any()
+    for i in range(37):
+        row = list(A.col[A.row_ptr[i]:A.row_ptr[i + 1]])
+        assert list(cl[rl[i]:rl[i + 1]]) == [c for c in row if c0 <= c < c1]
+        assert list(cn[rn[i]:rn[i + 1]]) == [c for c in row if not c0 <= c < c1]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_all_core_baseline_equals_the_serial_oracle_bitwise(dtype):
+    # the CPU baseline's threaded form runs each row's sum unchanged: the same bits as the
+    # serial definition, whatever the thread count
+    A = synth.hh_like(100003, seed=12).astype(dtype)
+    x = synth.dense_x(A.n_cols, 12)
+    y, used = oracle.csr_spmv_threads(A, x)
+    assert used >= 1
+    assert np.array_equal(y.view(np.uint64), oracle.csr_spmv(A, x).view(np.uint64))

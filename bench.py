@@ -5,24 +5,33 @@ Default workload: the Holstein-Hubbard-like matrix (N = 2^22 rows, banded symmet
 with contiguous off-diagonals, row lengths 5..20, N(0,1) values), FP64.  Default kernel
 configuration: the tuned pJDS form -- block height 64, rows sorted inside windows of 256
 (per-block layout), x staged in LDS per 1024-row tile with a halo of 768, two adjacent rows
-per lane, y written in the permuted basis (Listing 2).  The paper's plain configuration (global sort, jagged-diagonal
-layout) is timed beside it in `extra.autotune`.  One step is one product y = A x with the
-matrix and x already resident in HBM.
+per lane, y written in the permuted basis (Listing 2).  The paper's plain configuration (global
+sort, jagged-diagonal layout) is timed beside it in `extra.autotune`.
 
-Prints ONE JSON line.  `value` is the achieved bandwidth by the algorithmic byte count of
-the product, 12 B per non-zero (value + column index) plus 8 B per row for x and 8 B per
-row for y, divided by the measured time per product.
+One step is one product y = A x with the matrix and x already resident in HBM, run from a
+cold Infinity Cache: each step first streams 1 GiB of another buffer through the caches with
+ordinary loads (a read-only pass: it evicts the 256 MB cache and leaves nothing dirty), then
+runs the product between two HIP events on the product's stream.  `value` is the median over
+the timed steps of the algorithmic bytes of the product -- 12 B per non-zero (value + column
+index) plus 8 B per row for x and 8 B per row for y -- divided by the product's time;
+`roofline.achieved` the same bytes over the mean product time.  `warm` times the same product
+back to back (caches warm) for comparison.
+
+Every timed leg is checked against the oracle before the line is printed (the whole vector
+of the headline product, sampled rows of the others); a leg outside its tolerance (1e-12
+relative in binary64, 1e-5 in binary32) nulls `value`, names the leg in `error` and makes the
+exit status 1.
 
     python bench.py [--steps K] [--warmup W] [--workload hh_like|laplacian|powerlaw]
                     [--dtype f64|f32] [--sort-window W] [--x-halo H] [--tile-rows T] [--one-row]
                     [--lanes T] [--xcd-remap] [--no-cpu] [--no-extra] [--no-batch]
 
-Besides the headline line's own fields, `extra` holds the comparison legs (cold Infinity Cache,
-ELLPACK-R, CSR, SpMMV with X through the caches or staged in LDS, the 128 x 128 Laplacian's
-SpMMV against single products, the exhaustive and learned tuners, Lanczos steps, the host-link
-model, lanes per row, the local/non-local split, FP32 and the power-law matrix) and `batch` the
-512-matrix leg (persistent kernel with x through the caches or staged in LDS, per-member graph,
-direct launches).
+Besides the headline line's own fields, `extra` holds the comparison legs (ELLPACK-R, CSR,
+SpMMV with X through the caches or staged in LDS, the 128 x 128 Laplacian's SpMMV against
+single products, the exhaustive and learned tuners, Lanczos steps, the host-link model, lanes
+per row, the local/non-local split, FP32 and the power-law matrix) and `batch` the 512-matrix
+leg (persistent kernel with x through the caches or staged in LDS, per-member graph, direct
+launches).
 """
 from __future__ import annotations
 
@@ -39,6 +48,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FLUSH_DOUBLES = 1 << 27        # 1 GiB read-only pass before each cold product
+TOL = {"f64": 1e-12, "f32": 1e-5}
+# every source the headline kernel is compiled from: a counter record taken on other sources
+# is not reported
+KERNEL_SOURCES = ("paper_1112_5588_amd/csrc/spmv.hip", "paper_1112_5588_amd/csrc/device.h",
+                  "paper_1112_5588_amd/csrc/launch.h", "paper_1112_5588_amd/csrc/common.h", "include/pjds.h")
 
 
 def log(msg: str) -> None:
@@ -46,19 +61,22 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1112_5588_amd", "csrc", "spmv.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(rel.encode())
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload_key: str):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if it was taken
-    on the kernel source that is built now; otherwise None."""
+    on the kernel sources that are built now; otherwise None."""
     p = os.path.join(ROOT, "profiles", "pjds_spmv_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     e = d.get(workload_key)
-    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+    if not e or e.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
     return e.get("traffic_bytes_per_launch")
 
@@ -82,8 +100,8 @@ def make_workload(name: str, dtype: str):
 
 
 def time_launches(fn, steps: int, warmup: int):
-    """Average ms per call of `fn` over `steps` calls, bracketed by events on the stream the
-    kernels are launched on (torch's current stream)."""
+    """Average ms per call of `fn` over `steps` back-to-back calls, bracketed by events on the
+    stream the kernels are launched on (torch's current stream): caches warm."""
     import torch
     for _ in range(warmup):
         fn()
@@ -97,21 +115,127 @@ def time_launches(fn, steps: int, warmup: int):
     return s.elapsed_time(e) / steps
 
 
-def cpu_baseline(A, x, budget_s: float = 12.0):
-    """The oracle's serial CSR product timed on this host (1 core)."""
+class ColdTimer:
+    """Products timed from a cold Infinity Cache: before each one, a read-only pass over 1 GiB
+    of another buffer with cached loads (probe mode 2) evicts the caches without leaving dirty
+    lines behind; the product alone is bracketed by events on the same stream."""
+
+    def __init__(self, torch, lib):
+        self.torch, self.lib = torch, lib
+        self.buf = torch.ones(FLUSH_DOUBLES, dtype=torch.float64, device="cuda")
+        self.out = torch.empty(2048, dtype=torch.float64, device="cuda")
+
+    def flush(self) -> None:
+        self.lib.pjds_probe(2, self.buf, self.out, FLUSH_DOUBLES)
+
+    def times(self, fn, reps: int, warmup: int = 3) -> list:
+        torch = self.torch
+        for _ in range(warmup):
+            self.flush()
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for s0, s1 in ev:
+            self.flush()
+            s0.record()
+            fn()
+            s1.record()
+        torch.cuda.synchronize()
+        return [s0.elapsed_time(s1) for s0, s1 in ev]
+
+    def median(self, fn, reps: int = 20, warmup: int = 3) -> float:
+        return float(np.median(self.times(fn, reps, warmup)))
+
+
+def sample_rows(n: int, seed: int, count: int = 4096) -> np.ndarray:
+    """First and last 256 rows plus `count` seeded random rows."""
+    import synth
+    r = (synth.uniform01(seed, 1, count) * n).astype(np.int64)
+    return np.unique(np.concatenate([np.arange(min(256, n)), np.arange(max(0, n - 256), n), r]))
+
+
+def rel_err(y: np.ndarray, ref: np.ndarray) -> float:
+    """||y - ref|| / ||ref|| in binary64 (absolute when ref is zero)."""
+    d = float(np.linalg.norm(np.asarray(y, np.float64) - np.asarray(ref, np.float64)))
+    r = float(np.linalg.norm(np.asarray(ref, np.float64)))
+    return d / r if r > 0 else d
+
+
+def rows_in_original_order(torch, y_dev, rows: np.ndarray, perm_dev=None) -> np.ndarray:
+    """y's values for original rows `rows` (y in the permuted basis when perm_dev is given:
+    slot i holds original row perm[i])."""
+    torch.cuda.synchronize()
+    if perm_dev is None:
+        return y_dev.double()[torch.from_numpy(rows).to(y_dev.device)].cpu().numpy()
+    inv = torch.empty_like(perm_dev)
+    inv[perm_dev.long()] = torch.arange(perm_dev.numel(), dtype=perm_dev.dtype, device=perm_dev.device)
+    return y_dev.double()[inv[torch.from_numpy(rows).to(y_dev.device)].long()].cpu().numpy()
+
+
+# ---- the CPU leg: the oracle timed on this host, and the reference values of the checks ----
+
+def cpu_baseline_leg(A, x, b_alg: float, budget_s: float = 10.0):
+    """The oracle timed on this host's cores.  Its serial CSR product (the plain definition the
+    parity tests compare against) on one core: the median over full products within a budget
+    of about `budget_s` seconds, after 2 warm-ups.  Its all-core form (the same per-row sums,
+    bitwise the same result, rows shared among OpenMP threads): the median of 20 after 2
+    warm-ups.  Returns the serial result, the reference of the headline check."""
     import oracle
     t0 = time.perf_counter()
     y = oracle.csr_spmv(A, x)
-    first = time.perf_counter() - t0
-    reps = max(1, min(200, int(budget_s / max(first, 1e-4))))
-    t0 = time.perf_counter()
+    oracle.csr_spmv(A, x)
+    one = max((time.perf_counter() - t0) / 2, 1e-4)
+    reps = max(5, min(500, int(budget_s / one)))
+    ts = []
     for _ in range(reps):
+        t0 = time.perf_counter()
         oracle.csr_spmv(A, x)
-    dt = (time.perf_counter() - t0) / reps
-    return y, dt, reps
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    yt = np.empty_like(y)
+    for _ in range(2):
+        _, used = oracle.csr_spmv_threads(A, x, yt)
+    tt = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        _, used = oracle.csr_spmv_threads(A, x, yt)
+        tt.append(time.perf_counter() - t0)
+    dtt = float(np.median(tt))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    rec = {"value": round(b_alg / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"full matrix, median of {reps} serial CSR products (binary64, no FMA) after 2 warm-ups, {sum(ts):.1f} s",
+           "gflops": round(2 * A.nnz / dt / 1e9, 3), "ms_per_product": round(dt * 1e3, 3),
+           "all_cores": {"value": round(b_alg / dtt / 1e9, 3), "unit": "GB/s", "cores": int(used),
+                         "nproc": os.cpu_count(), "affinity": affinity,
+                         "sample": "full matrix, median of 20 products after 2 warm-ups, rows shared among OpenMP threads (bitwise the serial result)",
+                         "gflops": round(2 * A.nnz / dtt / 1e9, 3), "ms_per_product": round(dtt * 1e3, 3),
+                         "bitwise_equal_to_serial": bool(np.array_equal(yt, y))}}
+    return y, rec
 
 
-def batch_leg(torch) -> dict:
+def reference_rows(A, x, rows: np.ndarray) -> np.ndarray:
+    """The oracle's values of (A x) at original rows `rows` (X with k columns: (len(rows), k))."""
+    import oracle
+    rows = np.asarray(rows, np.int64)
+    rp = np.asarray(A.row_ptr, np.int64)
+    lens = rp[rows + 1] - rp[rows]
+    new_rp = np.zeros(len(rows) + 1, np.int64)
+    new_rp[1:] = np.cumsum(lens)
+    idx = np.repeat(rp[rows] - new_rp[:-1], lens) + np.arange(int(new_rp[-1]), dtype=np.int64)
+
+    class _S:
+        pass
+    S = _S()
+    S.n_rows, S.n_cols, S.row_ptr, S.col, S.val = len(rows), A.n_cols, new_rp, np.asarray(A.col)[idx], np.asarray(A.val)[idx]
+    S.nnz = int(new_rp[-1])
+    if np.ndim(x) == 2:
+        return oracle.csr_spmmv(S, x)
+    return oracle.csr_spmv(S, x)
+
+
+def batch_leg(torch, checks: dict) -> dict:
     """512 uneven matrices (rows log-uniform in [1e3, 5e5], 3..60 entries per row, columns
     within +-4096 of the diagonal), FP64: one persistent launch in a HIP graph (x through the
     caches, or staged in LDS per tile with a 4096-value halo) vs one launch per member captured
@@ -139,12 +263,23 @@ def batch_leg(torch) -> dict:
         b_alg = 12 * nnz + 16 * rows
         res = {"setup_s": round(t_setup, 1), "nnz_stored": sum(M.info.nnz_stored for M in mats)}
         out["rows"], out["nnz"] = rows, nnz
+        # two members against the oracle after every launch form (the numpy generator gives the
+        # same bits as the torch one)
+        refs = {}
+        for m in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+            Am = synth.banded_stratified(int(sizes[m]), 1000 + m)
+            refs[m] = reference_rows(Am, synth.dense_x(Am.n_cols, 1000 + m), np.arange(Am.n_rows))
         for name, mode, halo in (("persistent_graph", _lib.PJDS_BATCH_PERSISTENT, None),
                                  ("persistent_graph_x_in_lds", _lib.PJDS_BATCH_PERSISTENT, 4096),
                                  ("per_member_graph", _lib.PJDS_BATCH_GRAPH, None),
                                  ("direct_launches", _lib.PJDS_BATCH_DIRECT, None)):
+            for y in ys:
+                y.fill_(float("nan"))
             B = PjdsBatch(mats, xs, ys, mode=mode, y_permuted=True, x_halo=halo)
             ms = time_launches(B.launch, 10, 2)
+            for m, ref in refs.items():
+                checks[f"batch_{label}_{name}_m{m}"] = rel_err(
+                    rows_in_original_order(torch, ys[m], np.arange(len(ref)), mats[m].d["perm"]), ref)
             res[name] = {"ms": round(ms, 4), "gflops": round(2 * nnz / ms / 1e6, 1), "GBps_alg": round(b_alg / ms / 1e6, 1)}
             if mode == _lib.PJDS_BATCH_PERSISTENT:
                 res[name]["tiles"], res[name]["grid"] = B.info()
@@ -158,8 +293,8 @@ def batch_leg(torch) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="hh_like", choices=["hh_like", "laplacian", "powerlaw"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--block-height", type=int, default=64)
@@ -175,14 +310,14 @@ def main() -> int:
                     help="LDS path: one row per lane (default: two adjacent rows per lane, 2-wide loads)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="lanes per row (power of two up to 64, block layout, x through the caches)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline timing (the checks still run)")
     ap.add_argument("--no-extra", action="store_true", help="skip comparison legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-matrix batch leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path "
-                                   "of the paper is not built (one GPU per process, --gpus 1)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the paper's multi-GPU path is "
+                                   "not built here (one GPU per process); run with --gpus 1"}))
         return 2
 
     import torch
@@ -207,6 +342,7 @@ def main() -> int:
         x_np = x_np.astype(np.float32).astype(np.float64)
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     vbytes = 8 if args.dtype == "f64" else 4
+    tol = TOL[args.dtype]
 
     log(f"N={n} nnz={nnz} generated in {t_gen:.1f}s; converting")
     t0 = time.perf_counter()
@@ -221,38 +357,64 @@ def main() -> int:
     y_dev = torch.empty(n, dtype=tdt, device="cuda")
     y_perm = args.mode in ("y_permuted", "symmetric")
 
-    if args.x_halo >= 0:
-        def step():
-            M.spmv_xlds(x_dev, y_dev, x_halo=args.x_halo, tile_rows=args.tile_rows, y_permuted=y_perm,
+    def product(x, y):
+        if args.x_halo >= 0:
+            M.spmv_xlds(x, y, x_halo=args.x_halo, tile_rows=args.tile_rows, y_permuted=y_perm,
                         xcd_remap=args.xcd_remap, two_rows=args.two_rows)
-    else:
-        def step():
-            M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=args.xcd_remap)
+        else:
+            M.spmv(x, y, y_permuted=y_perm, xcd_remap=args.xcd_remap)
 
-    log("timing")
-    ms = time_launches(step, args.steps, args.warmup)
+    def step():
+        product(x_dev, y_dev)
+
     # algorithmic bytes: value + index per non-zero, x once, y once (write)
     b_alg = (vbytes + 4) * nnz + 2 * vbytes * n
     if args.mode == "scatter":
         b_alg += 4 * n               # the permutation read to scatter y
-    gbs = b_alg / (ms * 1e-3) / 1e9
-    gflops = 2 * nnz / (ms * 1e-3) / 1e9
 
-    # correctness gate on the full vector: the oracle's serial product
+    # ---- the timed region: W warm-up steps, then K steps, each a cold product
+    cold = ColdTimer(torch, _lib)
+    log(f"timing {args.steps} cold steps after {args.warmup} warm-ups")
+    for _ in range(args.warmup):
+        cold.flush()
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_wall = time.perf_counter()
+    for s0, s1 in ev:
+        cold.flush()
+        s0.record()
+        step()
+        s1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_steps = [s0.elapsed_time(s1) for s0, s1 in ev]
+    ms = float(np.median(ms_steps))
+    ms_mean = float(np.mean(ms_steps))
+    gbs = b_alg / (ms * 1e-3) / 1e9
+    gbs_mean = b_alg / (ms_mean * 1e-3) / 1e9
+    gflops = 2 * nnz / (ms * 1e-3) / 1e9
+    # the same product back to back, caches warm
+    ms_warm = time_launches(step, 200, 20)
+
+    # ---- checks: the headline against the oracle (whole vector), the CPU baseline
     out: dict = {}
+    checks: dict = {}
     cpu = None
     y = y_dev.double().cpu().numpy()
-    if y_perm:
-        ref_idx = M.d["perm"].cpu().numpy()
+    if args.mode == "symmetric":
+        ref_idx = M.host["perm"]
+    elif y_perm:
+        ref_idx = perm.cpu().numpy()
+    log("CPU oracle: reference and baseline timing")
     if not args.no_cpu:
-        log("CPU oracle baseline")
-        y_ref, dt_cpu, reps = cpu_baseline(A, x_np)
-        cpu = {"value": round(b_alg / dt_cpu / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"full matrix, {reps} serial CSR products (binary64, no FMA), median-free mean over {reps*dt_cpu:.1f}s",
-               "gflops": round(2 * nnz / dt_cpu / 1e9, 3), "ms_per_product": round(dt_cpu * 1e3, 3)}
-        yr = y_ref[ref_idx] if y_perm else y_ref
+        y_ref, cpu = cpu_baseline_leg(A, x_np, b_alg)
+    else:
         import oracle
-        out["rel_err_vs_oracle"] = oracle.rel_l2(y, yr)
+        y_ref = oracle.csr_spmv(A, x_np)
+    yr = y_ref[ref_idx] if y_perm else y_ref
+    checks["headline"] = out["rel_err_vs_oracle"] = rel_err(y, yr)
+    del y
 
     lanes_key = f"_T{args.lanes}" if args.lanes > 1 else ""
     if args.x_halo >= 0 and args.two_rows:
@@ -277,18 +439,24 @@ def main() -> int:
                    "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
                    "tile_rows": args.tile_rows if args.x_halo >= 0 else None,
                    "rows_per_lane": 2 if (args.x_halo >= 0 and args.two_rows) else 1,
-                   "split_len": M.info.split_len, "n_chunks": M.info.n_chunks},
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                   "split_len": M.info.split_len, "n_chunks": M.info.n_chunks,
+                   "protocol": "median of the steps' product times, each product after a 1 GiB read-only pass with cached loads (Infinity Cache cold)"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs_mean, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs_mean / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": ("pjds_spmv_lds2_kernel" if args.two_rows else "pjds_spmv_lds_kernel") if args.x_halo >= 0 else
                                ("pjds_lanes_kernel" if args.lanes > 1 else "pjds_spmv_kernel"),
-                     "alg_bytes_per_launch": b_alg},
+                     "alg_bytes_per_launch": b_alg, "mean_launch_ms": round(ms_mean, 5)},
         "cpu_baseline": cpu,
         "gflops": round(gflops, 2),
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "steps_ms": {"min": round(min(ms_steps), 5), "median": round(ms, 5), "mean": round(ms_mean, 5),
+                     "max": round(max(ms_steps), 5), "wall_s_timed_region": round(t_wall, 4)},
+        "warm": {"ms_mean": round(ms_warm, 5), "GBps_alg": round(b_alg / ms_warm / 1e6, 2),
+                 "frac": round(b_alg / ms_warm / 1e6 / HBM_PEAK_GBS, 4),
+                 "protocol": "mean of 200 back-to-back products after 20 warm-ups"},
         "conversion_s": round(t_conv, 3),
         "footprint_bytes": {"pjds": M.footprint_bytes()},
-        "kernel_source_sha256_16": kernel_source_hash(),
+        "kernel_sources_sha256_16": kernel_source_hash(),
     }
     result.update(out)
 
@@ -297,7 +465,7 @@ def main() -> int:
     nprobe = 1 << 28
     a = torch.empty(nprobe, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty(nprobe, dtype=torch.float64, device="cuda")
-    r = torch.empty(4096, dtype=torch.float64, device="cuda")
+    r = torch.empty(2048, dtype=torch.float64, device="cuda")
     ms_r = time_launches(lambda: _lib.pjds_probe(0, a, r, nprobe), 10, 2)
     ms_c = time_launches(lambda: _lib.pjds_probe(1, a, b, nprobe), 10, 2)
     result["hbm_probe"] = {"bytes_read": 8 * nprobe, "read_GBps": round(8 * nprobe / ms_r / 1e6, 1),
@@ -307,27 +475,18 @@ def main() -> int:
 
     if not args.no_extra:
         extra = {}
-        # cold Infinity Cache: the median of single products, each after a 1 GiB streaming
-        # pass over another buffer evicts the matrix and x from the 256 MB MALL
-        flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-        flush.fill_(1.0)
+        rows = sample_rows(n, 91)
+        ref_rows = y_ref[rows]
+        x_orig = torch.from_numpy(x_np).to("cuda", tdt)
 
-        def cold_median(fn, reps: int = 20) -> float:
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(reps + 1)]
-            for s0, s1 in ev:
-                flush.mul_(1.0)
-                s0.record()
-                fn()
-                s1.record()
-            torch.cuda.synchronize()
-            cold = sorted(s0.elapsed_time(s1) for s0, s1 in ev[1:])
-            return cold[len(cold) // 2]
+        def leg(name, fn, y_out, perm_dev=None, b=b_alg, flops=2 * nnz, ref=ref_rows, rws=rows, reps=20):
+            """Cold median and warm mean of one comparison leg, and its sampled rows checked."""
+            ms_c = cold.median(fn, reps)
+            ms_w = time_launches(fn, 50, 5)
+            checks[name] = rel_err(rows_in_original_order(torch, y_out, rws, perm_dev), ref)
+            return {"ms": round(ms_c, 5), "ms_warm": round(ms_w, 5), "GBps_alg": round(b / ms_c / 1e6, 1),
+                    "gflops": round(flops / ms_c / 1e6, 2), "rel_err_sampled": checks[name]}
 
-        ms_cold = cold_median(step)
-        extra["cold_mall"] = {"reps": 20, "median_ms": round(ms_cold, 5),
-                              "GBps_alg": round(b_alg / ms_cold / 1e6, 1)}
-        # same matrix in the comparison formats
         log("ELLPACK-R and CSR legs")
         info_e = EllrMatrix.plan(A)
         ebytes = info_e.nnz_stored * (vbytes + 4) + info_e.n_pad * 4
@@ -335,72 +494,74 @@ def main() -> int:
         result["footprint_bytes"]["csr"] = nnz * (vbytes + 4) + (n + 1) * 8
         if ebytes < 64 * 2 ** 30:
             E = EllrMatrix.from_csr(A)
-            xo = torch.from_numpy(x_np).to("cuda", tdt)
             ye = torch.empty(n, dtype=tdt, device="cuda")
-            ms_e = time_launches(lambda: E.spmv(xo, ye), 50, 5)
-            extra["ellpack_r"] = {"ms": round(ms_e, 5), "GBps_alg": round(((vbytes + 4) * nnz + 2 * vbytes * n) / ms_e / 1e6, 1),
-                                  "gflops": round(2 * nnz / ms_e / 1e6, 2)}
-            del E
+            extra["ellpack_r"] = leg("ellpack_r", lambda: E.spmv(x_orig, ye), ye)
+            del E, ye
         C = CsrMatrix.from_csr(A)
-        xo = torch.from_numpy(x_np).to("cuda", tdt)
         yc = torch.empty(n, dtype=tdt, device="cuda")
         for v in (1, 4, 16):
-            ms_c = time_launches(lambda: C.spmv(xo, yc, variant=v), 50, 5)
-            extra[f"csr_v{v}"] = {"ms": round(ms_c, 5), "GBps_alg": round(((vbytes + 4) * nnz + 2 * vbytes * n) / ms_c / 1e6, 1),
-                                  "gflops": round(2 * nnz / ms_c / 1e6, 2)}
-        del C
-        # scatter-y and XCD-renumbering variants of the headline kernel
-        ms_s = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=False), 50, 5)
-        ms_nr = time_launches(lambda: M.spmv(x_dev, y_dev, y_permuted=y_perm, xcd_remap=True), 50, 5)
-        extra["pjds_scatter_y"] = {"ms": round(ms_s, 5)}
-        extra["pjds_xcd_remap"] = {"ms": round(ms_nr, 5)}
+            extra[f"csr_v{v}"] = leg(f"csr_v{v}", lambda: C.spmv(x_orig, yc, variant=v), yc)
+        del C, yc
+        # scatter-y and XCD-renumbering variants of the plain kernel on the headline's storage
+        if args.mode != "symmetric":
+            ys_ = torch.empty(n, dtype=tdt, device="cuda")
+            extra["pjds_scatter_y"] = leg("pjds_scatter_y", lambda: M.spmv(x_dev, ys_, y_permuted=False), ys_)
+            extra["pjds_xcd_remap"] = leg("pjds_xcd_remap", lambda: M.spmv(x_dev, ys_, y_permuted=True, xcd_remap=True),
+                                          ys_, perm_dev=perm)
+            del ys_
         # many right-hand sides on the same matrix: the tile shape and XCD renumbering tuned
         # per k on two sort windows (256 keeps shared rows of X close; 4096 with renumbering lets
         # each XCD's L2 keep them), and X staged in LDS on windows of 256; effective GFLOP/s vs
         # the headline single-vector product
+        log("SpMMV leg")
         spmmv = {"plain_gflops": round(gflops, 2)}
         from paper_1112_5588_amd import autotune as _at
+        rows_k = rows[::4]
         for sw_k in (256, 4096):
             Mk = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw_k)
             for k in (4, 8, 16, 32):
                 (t, vpl, rmp), _ = _at.tune_spmmv(Mk, k, reps=3)
-                X = torch.from_numpy(synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)).to("cuda", tdt)
+                X_np = synth.dense_x(A.n_cols, 4, k=k).reshape(A.n_cols, k)
+                X = torch.from_numpy(X_np).to("cuda", tdt)
                 Y = torch.empty((n, k), dtype=tdt, device="cuda")
-                ms_k = time_launches(lambda: Mk.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl,
-                                                      y_permuted=True, xcd_remap=rmp), 20, 3)
-                if f"k{k}" not in spmmv or ms_k < spmmv[f"k{k}"]["ms"]:
-                    spmmv[f"k{k}"] = {"sort_window": sw_k, "tile": t, "vectors_per_lane": vpl, "xcd_remap": rmp,
-                                      "x_path": "caches",
-                                      "ms": round(ms_k, 5), "gflops": round(2 * k * nnz / ms_k / 1e6, 2),
-                                      "over_plain": round(2 * k * nnz / ms_k / 1e6 / gflops, 2)}
+                ref_k = reference_rows(A, X_np, rows_k)
+                bk = (vbytes + 4) * nnz + 2 * vbytes * n * k
+                r = leg(f"spmmv_k{k}_w{sw_k}", lambda: Mk.spmmv(X, Y, vectors_per_tile=t, vectors_per_lane=vpl,
+                                                                y_permuted=True, xcd_remap=rmp),
+                        Y, perm_dev=Mk.d["perm"], b=bk, flops=2 * k * nnz, ref=ref_k, rws=rows_k)
+                r.update({"sort_window": sw_k, "tile": t, "vectors_per_lane": vpl, "xcd_remap": rmp,
+                          "x_path": "caches", "over_plain": round(r["gflops"] / gflops, 2)})
+                if f"k{k}" not in spmmv or r["ms"] < spmmv[f"k{k}"]["ms"]:
+                    spmmv[f"k{k}"] = r
                 if sw_k == 256:
                     # X staged in LDS (pjds_spmmv_xlds): one vector tile of up to 8 vectors, since
                     # 64 KiB holds 1024 rows of 8 FP64 values (512-row tiles) or 2048 rows of 4
                     t_s = min(k, 8)
                     tile_s = 1024 if t_s * vbytes <= 32 else 512
-                    ms_s = time_launches(lambda: Mk.spmmv_xlds(X, Y, vectors_per_tile=t_s, vectors_per_lane=4,
-                                                               x_halo=512, tile_rows=tile_s, y_permuted=True), 20, 3)
-                    spmmv[f"k{k}_x_in_lds"] = {"tile": t_s, "tile_rows": tile_s, "x_halo": 512, "ms": round(ms_s, 5),
-                                               "gflops": round(2 * k * nnz / ms_s / 1e6, 2)}
-                    if ms_s < spmmv[f"k{k}"]["ms"]:
-                        spmmv[f"k{k}"] = {"sort_window": sw_k, "tile": t_s, "vectors_per_lane": 4, "xcd_remap": False,
-                                          "x_path": "lds", "tile_rows": tile_s, "x_halo": 512,
-                                          "ms": round(ms_s, 5), "gflops": round(2 * k * nnz / ms_s / 1e6, 2),
-                                          "over_plain": round(2 * k * nnz / ms_s / 1e6 / gflops, 2)}
+                    r = leg(f"spmmv_k{k}_lds", lambda: Mk.spmmv_xlds(X, Y, vectors_per_tile=t_s, vectors_per_lane=4,
+                                                                     x_halo=512, tile_rows=tile_s, y_permuted=True),
+                            Y, perm_dev=Mk.d["perm"], b=bk, flops=2 * k * nnz, ref=ref_k, rws=rows_k)
+                    r.update({"sort_window": sw_k, "tile": t_s, "vectors_per_lane": 4, "tile_rows": tile_s,
+                              "x_halo": 512, "x_path": "lds", "over_plain": round(r["gflops"] / gflops, 2)})
+                    spmmv[f"k{k}_x_in_lds"] = r
+                    if r["ms"] < spmmv[f"k{k}"]["ms"]:
+                        spmmv[f"k{k}"] = r
                 del X, Y
             del Mk
         extra["spmmv"] = spmmv
         # the small case (128 x 128 Laplacian): one SpMMV launch against k single products,
-        # launched one by one and replayed from a captured graph
+        # launched one by one and replayed from a captured graph (launch-bound: warm timing)
         L1 = synth.laplacian_2d(128)
         M1 = PjdsMatrix.from_csr(L1, block_height=64)
         small = {}
         for k in (1, 4, 8, 16, 32):
-            Xk = torch.from_numpy(synth.dense_x(L1.n_cols, 4, k=k).reshape(L1.n_cols, k)).cuda()
+            X1 = synth.dense_x(L1.n_cols, 4, k=k).reshape(L1.n_cols, k)
+            Xk = torch.from_numpy(X1).cuda()
             Yk = torch.empty((L1.n_rows, k), dtype=torch.float64, device="cuda")
             (t, vpl, rmp), _ = _at.tune_spmmv(M1, k, reps=5)
-            ms_mm = time_launches(lambda: M1.spmmv(Xk, Yk, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=True,
+            ms_mm = time_launches(lambda: M1.spmmv(Xk, Yk, vectors_per_tile=t, vectors_per_lane=vpl, y_permuted=False,
                                                    xcd_remap=rmp), 200, 20)
+            checks[f"laplacian_spmmv_k{k}"] = rel_err(Yk.cpu().numpy(), reference_rows(L1, X1, np.arange(L1.n_rows)))
             xs = [Xk[:, v].contiguous() for v in range(k)]
             ys = [torch.empty(L1.n_rows, dtype=torch.float64, device="cuda") for _ in range(k)]
 
@@ -420,15 +581,14 @@ def main() -> int:
             small[f"k{k}"] = {"spmmv_ms": round(ms_mm, 5), "spmmv_gflops": round(f / ms_mm, 2),
                               "singles_ms": round(ms_sep, 5), "singles_gflops": round(f / ms_sep, 2),
                               "singles_graph_ms": round(ms_gr, 5), "singles_graph_gflops": round(f / ms_gr, 2),
-                              "tile": t, "vectors_per_lane": vpl}
+                              "tile": t, "vectors_per_lane": vpl, "rel_err": checks[f"laplacian_spmmv_k{k}"]}
             del g1
         extra["spmmv_laplacian_128"] = small
         # exhaustive autotuner on this matrix: every catalog configuration, plus x in LDS
         from paper_1112_5588_amd import autotune
         log("autotuner leg")
-        xo = torch.from_numpy(x_np).to("cuda", tdt)
         t0_at = time.perf_counter()
-        t_cat = autotune.time_all(A, x=xo)
+        t_cat = autotune.time_all(A, x=x_orig)
         exhaustive_s = time.perf_counter() - t0_at
         # the learned tuner on the same matrix: features on the host, one network inference
         from paper_1112_5588_amd import tuner as _tn
@@ -445,7 +605,8 @@ def main() -> int:
             Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
             yw = torch.empty(n, dtype=tdt, device="cuda")
             lds[f"pjds_b64_w{sw}_lds{halo}_t{tile}"] = autotune.time_median(
-                lambda: Mw.spmv_xlds(xo, yw, x_halo=halo, tile_rows=tile, y_permuted=True), 20, 3)
+                lambda: Mw.spmv_xlds(x_orig, yw, x_halo=halo, tile_rows=tile, y_permuted=True), 20, 3)
+            checks[f"autotune_w{sw}_lds"] = rel_err(rows_in_original_order(torch, yw, rows, Mw.d["perm"]), ref_rows)
             del Mw
         t_all = {**t_cat, **lds}
         best = min(t_all, key=t_all.get)
@@ -475,13 +636,17 @@ def main() -> int:
                                                       y_permuted=True, two_rows=True), 50, 5)
             extra["lanczos"] = {"steps": steps, "ms_per_step_eager": round(ms_l / steps, 5),
                                 "ms_per_step_graph": round(ms_g / steps, 5), "ms_product_alone": round(ms_p, 5),
+                                "step_over_product": round(ms_g / steps / ms_p, 3),
                                 "vector_passes_per_step": 6,
                                 "GBps_alg_per_step": round((b_alg + 6 * 8 * n) / (ms_g / steps) / 1e6, 1)}
             del Ms, bufs, g
-        # host link (eq. 2-4): x to the device, the product, y back, from pinned host memory
+        # host link (eq. 2-4): x to the device, the product on that copy, y back, from pinned
+        # host memory
         xh = torch.from_numpy(x_np).to(tdt).pin_memory()
         yh = torch.empty(n, dtype=tdt).pin_memory()
-        xd2 = torch.empty(n, dtype=tdt, device="cuda")
+        xd2 = torch.empty_like(x_dev)
+        if args.mode == "symmetric":
+            xh = xh[perm.cpu().long()].contiguous().pin_memory()
 
         def h2d():
             xd2.copy_(xh, non_blocking=True)
@@ -493,9 +658,13 @@ def main() -> int:
 
         def with_link():
             xd2.copy_(xh, non_blocking=True)
-            step()
+            product(xd2, y_dev)
             yh.copy_(y_dev, non_blocking=True)
         ms_link = time_launches(with_link, 20, 3)
+        torch.cuda.synchronize()
+        yl = yh.double().numpy()
+        # y in the permuted basis: original row r sits at the inverse permutation's slot r
+        checks["host_link"] = rel_err(yl[np.argsort(ref_idx)][rows] if y_perm else yl[rows], ref_rows)
         from paper_1112_5588_amd import model as pmodel
         # eq. (2): B_GPU is the device's streaming bandwidth (the read probe), B_PCI the measured
         # round trip of x and y over the host link; alpha at its minimum 1/N_nzr
@@ -508,14 +677,15 @@ def main() -> int:
         extra["host_link"] = {
             "h2d_GBps": round(vbytes * n / ms_h2d / 1e6, 1), "d2h_GBps": round(vbytes * n / ms_d2h / 1e6, 1),
             "B_gpu_over_B_pci": round(ratio, 2), "n_nzr": round(nnzr, 2),
-            "ms_product": round(ms, 5), "ms_product_eq2": round(t_mvm_model * 1e3, 5),
+            "ms_product": round(ms_warm, 5), "ms_product_eq2": round(t_mvm_model * 1e3, 5),
             "ms_transfers_eq2": round(t_pci_model * 1e3, 5), "ms_with_transfers": round(ms_link, 5),
-            "transfer_share_measured": round(1 - ms / ms_link, 4),
+            "transfer_share_measured": round(1 - ms_warm / ms_link, 4),
             "transfer_share_eq2": round(t_pci_model / (t_pci_model + t_mvm_model), 4),
             "eq3_nnzr_max_half_penalty": {"alpha0": round(pmodel.nnzr_bound_half_penalty(ratio, 0.0), 1),
                                           "alpha1": round(pmodel.nnzr_bound_half_penalty(ratio, 1.0), 1)},
             "eq4_nnzr_min_tenth_penalty": {"alpha0": round(pmodel.nnzr_bound_tenth_penalty(ratio, 0.0), 1),
-                                           "alpha1": round(pmodel.nnzr_bound_tenth_penalty(ratio, 1.0), 1)}}
+                                           "alpha1": round(pmodel.nnzr_bound_tenth_penalty(ratio, 1.0), 1)},
+            "rel_err_sampled": checks["host_link"]}
         del xh, yh, xd2
         # T lanes per row (block layout, same sort window, x through the caches) on this matrix,
         # and the sliced formats the outlook names: rows sorted only inside each 64-row slice
@@ -523,11 +693,10 @@ def main() -> int:
         lanes_leg = {}
         for T, sw_l in ((2, args.sort_window), (4, args.sort_window), (8, args.sort_window), (1, 64), (4, 64)):
             Ml = PjdsMatrix.from_csr(A, layout="block", sort_window=sw_l, lanes=T)
-            xo = torch.from_numpy(x_np).to("cuda", tdt)
-            yl = torch.empty(n, dtype=tdt, device="cuda")
-            ms_t = time_launches(lambda: Ml.spmv(xo, yl, y_permuted=True), 50, 5)
-            lanes_leg[f"T{T}" if sw_l == args.sort_window else f"sliced_w{sw_l}_T{T}"] = {
-                "ms": round(ms_t, 5), "GBps_alg": round(b_alg / ms_t / 1e6, 1), "nnz_stored": Ml.info.nnz_stored}
+            yl_ = torch.empty(n, dtype=tdt, device="cuda")
+            key = f"T{T}" if sw_l == args.sort_window else f"sliced_w{sw_l}_T{T}"
+            lanes_leg[key] = leg(f"lanes_{key}", lambda: Ml.spmv(x_orig, yl_, y_permuted=True), yl_, perm_dev=Ml.d["perm"])
+            lanes_leg[key]["nnz_stored"] = Ml.info.nnz_stored
             del Ml
         extra["lanes_per_row"] = lanes_leg
         # local/non-local split (vector mode with overlap): y written, then read and written again
@@ -535,21 +704,20 @@ def main() -> int:
         loc, nl = split_columns(A, 0, A.n_cols // 2)
         ML, MN = PjdsMatrix.from_csr(loc), PjdsMatrix.from_csr(nl)
         M1 = PjdsMatrix.from_csr(A)
-        xo = torch.from_numpy(x_np).to("cuda", tdt)
         yo = torch.empty(n, dtype=tdt, device="cuda")
 
         def split_step():
-            ML.spmv(xo, yo)
-            MN.spmv_axpby(xo, yo, alpha=1.0, beta=1.0, z=yo)
-        ms_split = time_launches(split_step, 30, 3)
-        ms_one = time_launches(lambda: M1.spmv(xo, yo), 30, 3)
-        from paper_1112_5588_amd import model as pmodel
+            ML.spmv(x_orig, yo)
+            MN.spmv_axpby(x_orig, yo, alpha=1.0, beta=1.0, z=yo)
+        split_r = leg("split_local_nonlocal", split_step, yo)
+        one_r = leg("split_reference_single", lambda: M1.spmv(x_orig, yo), yo)
         nnzr = nnz / n
         extra["split_local_nonlocal"] = {
-            "ms_split": round(ms_split, 5), "ms_single": round(ms_one, 5),
-            "penalty": round(ms_split / ms_one - 1, 4),
-            "model_penalty_eq1": round((8.0 / nnzr) / pmodel.code_balance_dp(1.0 / nnzr, nnzr), 4)}
-        del ML, MN, M1
+            "ms_split": split_r["ms"], "ms_single": one_r["ms"],
+            "penalty": round(split_r["ms"] / one_r["ms"] - 1, 4),
+            "model_penalty_eq1": round((8.0 / nnzr) / pmodel.code_balance_dp(1.0 / nnzr, nnzr), 4),
+            "rel_err_sampled": split_r["rel_err_sampled"]}
+        del ML, MN, M1, loc, nl
         extra["autotune"] = {"ms": {k: round(v, 5) for k, v in t_all.items()}, "best": best,
                              "best_GBps_alg": round(b_alg / t_all[best] / 1e6, 1),
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
@@ -565,26 +733,33 @@ def main() -> int:
             A32 = A.astype(np.float32)
             M32 = PjdsMatrix.from_csr(A32, block_height=args.block_height, layout=args.layout,
                                       sort_window=args.sort_window)
-            x32 = torch.from_numpy(x_np).to("cuda", torch.float32)
+            x32_np = x_np.astype(np.float32)
+            x32 = torch.from_numpy(x32_np).to("cuda")
             y32 = torch.empty(n, dtype=torch.float32, device="cuda")
-            if args.x_halo >= 0:
-                ms32 = time_launches(lambda: M32.spmv_xlds(x32, y32, x_halo=args.x_halo, tile_rows=args.tile_rows,
-                                                           y_permuted=True, two_rows=args.two_rows), 100, 10)
-            else:
-                ms32 = time_launches(lambda: M32.spmv(x32, y32, y_permuted=True), 100, 10)
             b32 = 8 * nnz + 8 * n
-            extra["fp32"] = {"ms": round(ms32, 5), "GBps_alg": round(b32 / ms32 / 1e6, 1),
-                             "gflops": round(2 * nnz / ms32 / 1e6, 2), "alg_bytes": b32}
+            ref32 = reference_rows(A32, x32_np.astype(np.float64), rows)
+            if args.x_halo >= 0:
+                fn32 = lambda: M32.spmv_xlds(x32, y32, x_halo=args.x_halo, tile_rows=args.tile_rows,  # noqa: E731
+                                             y_permuted=True, two_rows=args.two_rows)
+            else:
+                fn32 = lambda: M32.spmv(x32, y32, y_permuted=True)  # noqa: E731
+            r = leg("fp32", fn32, y32, perm_dev=M32.d["perm"], b=b32, ref=ref32)
+            r["alg_bytes"] = b32
+            extra["fp32"] = r
             del A32, M32, x32, y32
         # the skewed-row workload: global sort vs sort windows 2^10..2^16 (padding and time),
         # several lanes per row, and ELLPACK-R's padded size (planned, not allocated)
         log("power-law leg")
-        del M, x_dev, y_dev
+        del M, x_dev, y_dev, x_orig
         torch.cuda.empty_cache()
         P, _ = make_workload("powerlaw", args.dtype)
-        xp = torch.from_numpy(synth.dense_x(P.n_cols, 3)).to("cuda", tdt)
+        xp_np = synth.dense_x(P.n_cols, 3)
+        if args.dtype == "f32":
+            xp_np = xp_np.astype(np.float32).astype(np.float64)
+        xp = torch.from_numpy(xp_np).to("cuda", tdt)
         yp_ = torch.empty(P.n_rows, dtype=tdt, device="cuda")
         bp = (vbytes + 4) * P.nnz + 2 * vbytes * P.n_rows
+        rows_p = sample_rows(P.n_rows, 93)
         pl = {"nnz": P.nnz, "ellpack_r_stored": EllrMatrix.plan(P).nnz_stored}
         for label, kw in (("global_split512", dict(layout="block", split_len=512)),
                           ("global_nosplit", dict(layout="block", split_len=-1)),
@@ -597,23 +772,30 @@ def main() -> int:
                           # ELLPACK, and with 4 lanes per row that of sliced ELLR-T
                           ("sliced_ellpack_w64", dict(layout="block", sort_window=64, split_len=512)),
                           ("sliced_ellr_t4_w64", dict(layout="block", sort_window=64, lanes=4))):
-            Mp = PjdsMatrix.from_csr(P, **kw)
-            ms_p = time_launches(lambda: Mp.spmv(xp, yp_, y_permuted=True), 20, 3)
-            pl[label] = {"ms": round(ms_p, 5), "GBps_alg": round(bp / ms_p / 1e6, 1),
-                         "nnz_stored": Mp.info.nnz_stored,
-                         "padding": round(Mp.info.nnz_stored / P.nnz - 1, 4)}
-            if label == "global_split512":        # cold-cache protocol: x (64 MB) evicted too
-                ms_c = cold_median(lambda: Mp.spmv(xp, yp_, y_permuted=True))
-                pl[label]["cold_mall_median_ms"] = round(ms_c, 5)
-                pl[label]["cold_mall_GBps_alg"] = round(bp / ms_c / 1e6, 1)
+            Mp = PjdsMatrix.from_csr(P, keep_host=True, **kw)
+            if label == "global_split512":
+                # the longest rows (split into work items) join the sampled rows
+                rows_p = np.unique(np.concatenate([rows_p, Mp.host["perm"][:2048].astype(np.int64)]))
+                ref_p = reference_rows(P, xp_np, rows_p)
+            r = leg(f"powerlaw_{label}", lambda: Mp.spmv(xp, yp_, y_permuted=True), yp_, perm_dev=Mp.d["perm"],
+                    b=bp, flops=2 * P.nnz, ref=ref_p, rws=rows_p)
+            r.update({"nnz_stored": Mp.info.nnz_stored, "padding": round(Mp.info.nnz_stored / P.nnz - 1, 4)})
+            pl[label] = r
             del Mp
         extra["powerlaw"] = pl
-        del P, xp, yp_, flush
+        del P, xp, yp_
         result["extra"] = extra
     if not args.no_batch:
         torch.cuda.empty_cache()
-        result["batch"] = batch_leg(torch)
+        result["batch"] = batch_leg(torch, checks)
 
+    result["checks"] = {"tolerance": tol, "rel_err": {k: float(f"{v:.3e}") for k, v in checks.items()}}
+    bad = [k for k, v in checks.items() if not v <= tol]
+    if bad:
+        result["error"] = f"outside the {tol:g} relative-error tolerance: {', '.join(bad)}"
+        result["value"] = None
+        print(json.dumps(result), flush=True)
+        return 1
     print(json.dumps(result), flush=True)
     return 0
 

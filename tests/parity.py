@@ -113,3 +113,30 @@ def assert_rows_axpby(y, A, x, a: float, b: float, z, value_bytes: int = 8, rows
     rel = oracle.rel_l2(y, ref)
     assert rel <= (tol if tol is not None else TOL[value_bytes]), rel
     return rel
+
+
+class RowReference:
+    """The oracle's A x, sum of |a_ij x_j| and row lengths of one matrix and x, computed once and
+    checked against several results (full-size matrices with many product forms)."""
+
+    def __init__(self, A, x):
+        self.A = A
+        self.x = np.asarray(x, np.float64)
+        self.ref = oracle.csr_spmv(A, self.x)
+        self.mag = oracle.csr_spmv(_abs(A), np.abs(self.x))
+        self.L = np.diff(np.asarray(A.row_ptr, np.int64))
+
+    def check(self, y, value_bytes: int = 8, rows=None, extra_terms: int = 0, tol: float | None = None) -> float:
+        """y holds rows ``rows`` of A x (all rows when None), in that order."""
+        sel = slice(None) if rows is None else np.asarray(rows)
+        ref, mag, L = self.ref[sel], self.mag[sel], self.L[sel] + extra_terms
+        y = np.asarray(y, np.float64).ravel()
+        bound = (gamma(L, _unit(value_bytes)) + gamma(L, U64)) * mag * (1.0 + 2.0 * gamma(L, U64))
+        err = np.abs(y - ref)
+        bad = np.flatnonzero(~(err <= bound))
+        assert bad.size == 0, (f"{bad.size} rows outside the per-row bound; first: row "
+                               f"{int(bad[0]) if rows is None else int(np.asarray(rows)[bad[0]])} "
+                               f"|dy| = {err[bad[0]]:.3e} > {bound[bad[0]]:.3e}")
+        rel = oracle.rel_l2(y, ref)
+        assert rel <= (tol if tol is not None else TOL[value_bytes]), rel
+        return rel

@@ -400,6 +400,7 @@ def main() -> int:
     # ---- checks: the headline against the oracle (whole vector), the CPU baseline
     out: dict = {}
     checks: dict = {}
+    tol_of: dict = {}                   # legs computed in another precision than the headline
     cpu = None
     y = y_dev.double().cpu().numpy()
     if args.mode == "symmetric":
@@ -744,6 +745,7 @@ def main() -> int:
             else:
                 fn32 = lambda: M32.spmv(x32, y32, y_permuted=True)  # noqa: E731
             r = leg("fp32", fn32, y32, perm_dev=M32.d["perm"], b=b32, ref=ref32)
+            tol_of["fp32"] = TOL["f32"]
             r["alg_bytes"] = b32
             extra["fp32"] = r
             del A32, M32, x32, y32
@@ -789,10 +791,11 @@ def main() -> int:
         torch.cuda.empty_cache()
         result["batch"] = batch_leg(torch, checks)
 
-    result["checks"] = {"tolerance": tol, "rel_err": {k: float(f"{v:.3e}") for k, v in checks.items()}}
-    bad = [k for k, v in checks.items() if not v <= tol]
+    result["checks"] = {"tolerance": tol, "tolerance_per_leg": tol_of,
+                        "rel_err": {k: float(f"{v:.3e}") for k, v in checks.items()}}
+    bad = [k for k, v in checks.items() if not v <= tol_of.get(k, tol)]
     if bad:
-        result["error"] = f"outside the {tol:g} relative-error tolerance: {', '.join(bad)}"
+        result["error"] = f"outside the relative-error tolerance: {', '.join(bad)}"
         result["value"] = None
         print(json.dumps(result), flush=True)
         return 1

@@ -34,6 +34,10 @@ struct EpiArgs {
     const void *beta_dev = nullptr;   // if set, b = bscale * (*beta_dev) read on the device
     double bscale = 0.0;
     const void *alpha_dev = nullptr;  // if set, the factor of A x is *alpha_dev, read on the device
+    // if set (x staged in LDS, two rows per lane, a square matrix in the permuted basis, y
+    // permuted): workgroup t of the product writes sum over its rows i of y_i * x_i to
+    // dot_partial[t], in a fixed order (binary64)
+    double *dot_partial = nullptr;
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -9,15 +9,20 @@
 //
 //     w = (1/s_j) A u_j - (beta_j / s_{j-1}) u_{j-1}   one pJDS product, both factors applied
 //                                                     in its epilogue
-//     alpha_j = (w . u_j) / s_j                       deterministic two-stage reduction
+//     alpha_j = (w . u_j) / s_j                       deterministic two-stage reduction; with
+//                                                     x staged in LDS the product's workgroups
+//                                                     sum w_i u_j[i] over their own rows (u_j[i]
+//                                                     is staged) and one small kernel adds the
+//                                                     partial sums
 //     w = w - (alpha_j / s_j) u_j;  t = w . w         one pass
 //     beta_{j+1} = sqrt(t);  u_{j+1} = w
 //
 // Every scalar stays in device memory and every kernel reads it there, so a step needs no
 // host synchronisation and a sequence of steps can be captured in a graph.  Reductions use a
-// fixed grid and fixed summation trees: results are reproducible bit for bit.  Six vector
-// passes per step besides the product's own x and y traffic (z read, w and u_j read twice,
-// w written once).
+// fixed grid and fixed summation trees: results are reproducible bit for bit.  Vector passes
+// per step besides the product's own x and y traffic: four with x staged in LDS (z read; w
+// and u_j read and w written by the update), six with x through the caches (w and u_j read
+// once more for alpha).
 #include <algorithm>
 #include <cmath>
 
@@ -75,12 +80,12 @@ __global__ __launch_bounds__(kRedThreads) void axpy_norm_partial_kernel(int64_t 
 //            zc_next[0] = b * inv_s[0]                          beta_{j+1} / s_j)
 //   kNorm:   inv_next[0] = 1 / sqrt(sum)                       (1 / s_0)
 enum FinishMode { kAlpha = 0, kBeta = 1, kNorm = 2 };
-__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, int mode,
-                                                             const double *inv_s, double *out, double *inv_next,
-                                                             double *zc_next) {
+__global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__restrict__ partial, int64_t n_part,
+                                                             int mode, const double *inv_s, double *out,
+                                                             double *inv_next, double *zc_next) {
     __shared__ double red[kRedThreads];
     double s = 0.0;
-    for (int q = threadIdx.x; q < kRedBlocks; q += kRedThreads) s += partial[q];
+    for (int64_t q = threadIdx.x; q < n_part; q += kRedThreads) s += partial[q];
     const double t = block_sum(s, red);
     if (threadIdx.x != 0) return;
     if (mode == kAlpha) {
@@ -94,6 +99,10 @@ __global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__res
         inv_next[0] = 1.0 / sqrt(t);
     }
 }
+
+// Partial sums a step can leave: the reduction grid's, or one per row tile of the staged
+// product (tiles of at least 256 rows).
+int64_t partial_slots(const pjds_info &in) { return std::max<int64_t>(kRedBlocks, ceil_div(in.n_pad, 256)); }
 
 __global__ void fill_kernel(int64_t n, double *p, double v) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
@@ -109,7 +118,7 @@ extern "C" {
 int pjds_lanczos_workspace(const pjds_info *info, int64_t *vector_bytes, int64_t *scratch_bytes) {
     if (!info || !vector_bytes || !scratch_bytes) return fail(PJDS_ERR_ARG, "NULL argument");
     *vector_bytes = 3 * std::max<int64_t>(info->n_rows, 1) * int64_t(sizeof(double));
-    *scratch_bytes = (kRedBlocks + 8) * int64_t(sizeof(double));
+    *scratch_bytes = (partial_slots(*info) + 8) * int64_t(sizeof(double));
     return PJDS_OK;
 }
 
@@ -136,12 +145,12 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
     double *V = static_cast<double *>(d_vectors);
     double *part = static_cast<double *>(d_scratch);
     // device scalars, two slots each (step j reads slot j % 2, its last kernel writes the other)
-    double *inv_s = part + kRedBlocks;          // 1 / s_j
+    double *inv_s = part + partial_slots(in);   // 1 / s_j
     double *zc = inv_s + 2;                     // beta_j / s_{j-1}
     // 1 / s_0 = 1 / |v|, beta_0 = 0
     hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kNorm), nullptr, nullptr, inv_s,
-                       nullptr);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int64_t(kRedBlocks), int(kNorm), nullptr,
+                       nullptr, inv_s, nullptr);
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, int64_t(1), d_beta, 0.0);
     for (int32_t j = 0; j < steps; ++j) {
         // u_0 is the caller's v (read only); then w of step j lands in V[(j + 1) % 3], which
@@ -156,19 +165,24 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
         ea.z = uprev;
         ea.beta_dev = zc + (j & 1);
         ea.bscale = -1.0;
-        if (x_halo >= 0)
+        int64_t n_part = kRedBlocks;
+        if (x_halo >= 0) {
+            // w . u_j as per-tile partial sums in the product's epilogue
+            ea.dot_partial = part;
+            n_part = xlds_tiles(in, tile_rows);
             launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, uj, w, x_halo, tile_rows, ea,
                         PJDS_Y_PERMUTED | PJDS_TWO_ROWS, s);
-        else
+        } else {
             launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, uj, w, ea,
                             PJDS_Y_PERMUTED, s);
-        hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kAlpha), inv_j, d_alpha + j,
-                           nullptr, nullptr);
+            hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part);
+        }
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, n_part, int(kAlpha), inv_j,
+                           d_alpha + j, nullptr, nullptr);
         hipLaunchKernelGGL(axpy_norm_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, d_alpha + j,
                            inv_j, part);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int(kBeta), inv_j, d_beta + j + 1,
-                           inv_n, zc + ((j + 1) & 1));
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int64_t(kRedBlocks), int(kBeta), inv_j,
+                           d_beta + j + 1, inv_n, zc + ((j + 1) & 1));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(PJDS_ERR_HIP, "pjds_lanczos: %s", hipGetErrorString(e));

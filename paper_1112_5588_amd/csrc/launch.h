@@ -10,6 +10,9 @@ namespace pjds {
 // Sizes, dtype and block height of a pJDS matrix usable by the single-vector product.
 int check_product_info(const pjds_info *info, int32_t dtype);
 int check_xlds(const pjds_info &in, int32_t dtype, int32_t x_halo, int32_t tile_rows);
+// Workgroups (row tiles) of the staged product: one per tile, the tile index = its rows / tile.
+int64_t xlds_tiles(const pjds_info &in, int32_t tile_rows);
+// ea.dot_partial needs PJDS_TWO_ROWS (the two-rows kernel computes it).
 void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets, const int32_t *d_col_p,
                  const void *d_val_p, const int32_t *d_perm, int32_t dtype, const void *d_x, void *d_y,
                  int32_t x_halo, int32_t tile_rows, const EpiArgs &ea, uint32_t flags, hipStream_t s);

@@ -100,7 +100,35 @@ struct XStaged {
     __device__ T operator()(int32_t c) const {
         return staged_or_global<T>(lds, uint32_t(int64_t(c) - lo), n, 1, x, c);
     }
+    // Two phases for a group of reads: every LDS read first, then the global reads of the
+    // columns outside the staged range.  A global read writes the register of its LDS read
+    // and must wait for it to land; issued after all of them, only the first such wait costs.
+    template <int K>
+    __device__ __forceinline__ void group(T (&v)[K], const int32_t (&c)[K]) const {
+        typedef __attribute__((address_space(3))) const T LdsT;
+        bool out[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t d = uint32_t(int64_t(c[k]) - lo);
+            out[k] = d >= n;
+            v[k] = ((const LdsT *)lds)[out[k] ? 0u : d];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (out[k]) v[k] = x[c[k]];
+    }
 };
+
+// Reads of a group through the caches (XGlobal): one gather per entry.
+template <class T, int K>
+__device__ __forceinline__ void gather_group(const XGlobal<T> &xr, T (&v)[K], const int32_t (&c)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = xr(c[k]);
+}
+template <class T, int K>
+__device__ __forceinline__ void gather_group(const XStaged<T> &xr, T (&v)[K], const int32_t (&c)[K]) {
+    xr.group(v, c);
+}
 
 // What a product writes: y[r] = alpha * (A x)[r] + b * z[r], with b = beta, or b = bscale *
 // (*beta_dev) when the coefficient lives in device memory (an iterative solver's scalar that
@@ -113,6 +141,7 @@ struct Epilogue {
     const T *beta_dev;
     T bscale;
     const T *alpha_dev;                 // if set, alpha = *alpha_dev
+    double *dot;                        // if set, per-workgroup sums of y_i * x_i (staged products)
     __device__ T operator()(T acc, int64_t r) const {
         const T a = alpha_dev ? alpha_dev[0] : alpha;
         if (!z) return a * acc;
@@ -122,8 +151,8 @@ struct Epilogue {
     // y[r] = (*this)(acc, r).  The plain product's y is written once and not read back by the
     // kernel, so it is stored non-temporally (keeps the caches for x); a solver's update, whose
     // result the next kernel reads at once, is stored normally.
-    __device__ void store(T *y, int64_t r, T acc) const {
-        const T v = (*this)(acc, r);
+    __device__ void store(T *y, int64_t r, T acc) const { put(y, r, (*this)(acc, r)); }
+    __device__ void put(T *y, int64_t r, T v) const {
         if (!z && !alpha_dev) __builtin_nontemporal_store(v, y + r);
         else y[r] = v;
     }
@@ -234,6 +263,88 @@ __device__ __forceinline__ void row_group_sum(T (&acc)[R], int64_t base, int64_t
     if (r > 2) row_steps_r<4, true, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
     else if (r == 2) row_steps_r<2, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
     else if (r == 1) row_steps_r<1, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
+}
+
+// R rows per lane with the next group of steps loading while the current one gathers: the
+// values and indices of steps [jb + U, jb + 2U) are issued after the gathers of steps
+// [jb, jb + U) and before their FMAs, so a wave keeps a group of matrix loads in flight while
+// it waits for x.  The loop body is one block with a fixed number of loads behind the
+// gathers, so the FMAs wait for the gathers only.  Every group is U steps wide; steps at or
+// past the wave's longest row m re-read step m - 1 (lines already fetched) and are masked,
+// so no load reaches past the longest row.  Same FMAs in the same order per row as
+// row_group_sum.
+template <int U, int R, class T>
+struct StepGroup {
+    typedef typename VecR<T, R>::type V;
+    typedef typename IdxR<R>::type I;
+    V v[U];
+    I c[U];
+    template <class Addr>
+    __device__ __forceinline__ void load(int jb, int m, int len0, int64_t base, int64_t base_lead, const Addr &addr,
+                                         const int32_t *__restrict__ col_p, const T *__restrict__ val_p) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = min(jb + u, m - 1);
+            const int64_t a = addr(j, j < len0 ? base : base_lead);
+            v[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(val_p + a));
+            c[u] = __builtin_nontemporal_load(reinterpret_cast<const I *>(col_p + a));
+        }
+    }
+    template <class XR>
+    __device__ __forceinline__ void gather(T (&xv)[U * R], const XR &xr) const {
+        int32_t cc[U * R];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < R; ++q) cc[u * R + q] = c[u][q];
+        gather_group(xr, xv, cc);
+    }
+    __device__ __forceinline__ void fma(T (&acc)[R], const T (&xv)[U * R], int jb, const int (&len)[R]) const {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const T s = __builtin_fma(v[u][q], xv[u * R + q], acc[q]);
+                acc[q] = jb + u < len[q] ? s : acc[q];
+            }
+    }
+};
+
+template <int R, class T, class Addr, class XR>
+__device__ __forceinline__ void row_group_sum_pipe(T (&acc)[R], int64_t base, int64_t base_lead, const int (&len)[R],
+                                                   int m, const Addr &addr, const int32_t *__restrict__ col_p,
+                                                   const T *__restrict__ val_p, const XR &xr) {
+    constexpr int U = R >= 4 ? 2 : 4;
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = T(0);
+    if (m <= 0) return;
+    // two register sets in turn, so the loads in flight never have to land for a copy
+    StepGroup<U, R, T> ga, gb;
+    auto step = [&](const StepGroup<U, R, T> &cur, StepGroup<U, R, T> &nxt, int jb) {
+        T xv[U * R];
+        cur.gather(xv, xr);
+        nxt.load(jb + U, m, len[0], base, base_lead, addr, col_p, val_p);
+        __builtin_amdgcn_sched_barrier(0);      // keep every next-group load ahead of the FMAs
+        cur.fma(acc, xv, jb, len);
+    };
+    auto last = [&](const StepGroup<U, R, T> &cur, int jb) {
+        T xv[U * R];
+        cur.gather(xv, xr);
+        cur.fma(acc, xv, jb, len);
+    };
+    ga.load(0, m, len[0], base, base_lead, addr, col_p, val_p);
+    const int groups = (m + U - 1) / U;
+    int k = 1, jb = 0;
+    for (; k + 1 < groups; k += 2, jb += 2 * U) {
+        step(ga, gb, jb);
+        step(gb, ga, jb + U);
+    }
+    if (k < groups) {
+        step(ga, gb, jb);
+        last(gb, jb + U);
+    } else {
+        last(ga, jb);
+    }
 }
 
 template <class T, bool JD, int BR>
@@ -425,24 +536,41 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
     __syncthreads();
     const XStaged<T> xr{x, xs, lo, uint32_t(hi > lo ? hi - lo : 0)};
     const bool y_perm = flags & PJDS_Y_PERMUTED;
+    double dsum = 0.0;                  // this thread's rows' y_i * x_i (epi.dot only)
     for (int64_t rb = r0;;) {
         int len[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) len[q] = lv[q];
         const int m = wave_first(len[0]);
         T acc[R];
-        row_group_sum<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, xr);
+        row_group_sum_pipe<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, xr);
 #pragma unroll
         for (int q = 0; q < R; ++q)
             if (i + q < n_rows) {
                 const int64_t r = y_perm ? i + q : perm[i + q];
-                epi.store(y, r, acc[q]);
+                const T v = epi(acc[q], r);
+                epi.put(y, r, v);
+                // a square matrix in the permuted basis: row i's own entry of x is staged
+                if (epi.dot) dsum = __builtin_fma(double(v), double(xs[i + q - lo]), dsum);
             }
         rb += int64_t(R) * NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
         i = rb + R * int64_t(threadIdx.x);
         lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
         base = addr.base(i < n_pad ? i : n_pad - R);
+    }
+    if (epi.dot) {
+        // fixed-order workgroup sum: butterfly inside each wave, then the waves in order
+        __shared__ double wsum[NT / kWave];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off);
+        if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = dsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NT / kWave; ++w) t += wsum[w];
+            epi.dot[r0 / tile] = t;
+        }
     }
 }
 
@@ -658,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__rest
 template <class T>
 Epilogue<T> make_epi(const EpiArgs &a) {
     return Epilogue<T>{T(a.alpha), T(a.beta), static_cast<const T *>(a.z), static_cast<const T *>(a.beta_dev),
-                       T(a.bscale), static_cast<const T *>(a.alpha_dev)};
+                       T(a.bscale), static_cast<const T *>(a.alpha_dev), a.dot_partial};
 }
 
 int launch_status(const char *what) {
@@ -845,6 +973,11 @@ int check_xlds(const pjds_info &in, int32_t dtype, int32_t x_halo, int32_t tile_
     const int64_t cap = std::min<int64_t>(std::max(tile, w) + 2 * int64_t(x_halo), in.n_cols);
     if (cap * tsize > 64 * 1024) return fail(PJDS_ERR_ARG, "x range of %lld entries exceeds 64 KiB of LDS", (long long)cap);
     return PJDS_OK;
+}
+
+int64_t xlds_tiles(const pjds_info &in, int32_t tile_rows) {
+    const int64_t tile = tile_rows == 0 ? std::max<int64_t>(in.sort_window, 1024) : tile_rows;
+    return ceil_div(in.n_pad, tile);
 }
 
 void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets, const int32_t *d_col_p,

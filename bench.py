@@ -635,11 +635,14 @@ def main() -> int:
             ys = torch.empty(n, dtype=torch.float64, device="cuda")
             ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=args.x_halo, tile_rows=args.tile_rows,
                                                       y_permuted=True, two_rows=True), 50, 5)
+            # vector passes besides the product's x and y: z read, w and u_j read and w written by
+            # the update; w and u_j read once more for alpha when x is not staged in LDS
+            passes = 4 if args.x_halo >= 0 else 6
             extra["lanczos"] = {"steps": steps, "ms_per_step_eager": round(ms_l / steps, 5),
                                 "ms_per_step_graph": round(ms_g / steps, 5), "ms_product_alone": round(ms_p, 5),
                                 "step_over_product": round(ms_g / steps / ms_p, 3),
-                                "vector_passes_per_step": 6,
-                                "GBps_alg_per_step": round((b_alg + 6 * 8 * n) / (ms_g / steps) / 1e6, 1)}
+                                "vector_passes_per_step": passes,
+                                "GBps_alg_per_step": round((b_alg + passes * 8 * n) / (ms_g / steps) / 1e6, 1)}
             del Ms, bufs, g
         # host link (eq. 2-4): x to the device, the product on that copy, y back, from pinned
         # host memory

@@ -174,6 +174,29 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
               uint32_t flags, void *stream);
 
 /*
+ * pjds_spmv for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same product, kernels and
+ * results (bitwise) as pjds_spmv, with the long-row workspace taken from a fixed array in the
+ * library's own device memory instead of a d_work argument.  Nothing is allocated, by the
+ * library or by anything it calls.
+ *   Arguments as for pjds_spmv, without d_work.
+ *   Limit: the workspace pjds_workspace_size reports for `info` must not exceed
+ *   PJDS_NOALLOC_SCRATCH_BYTES (16 MiB); larger plans are rejected with PJDS_ERR_OVERFLOW
+ *   before anything is launched.  Each GPU the library runs on holds one such array until
+ *   the process ends; its address is looked up on the first call made with that device
+ *   current, so call with the stream's device current.
+ *   Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ *   (different streams, or several host threads) race and give wrong results.  Each call
+ *   clears the completion counters it uses (a fill kernel on `stream`, no memset) before the
+ *   product, so a call never depends on what an earlier one left behind.
+ */
+#define PJDS_NOALLOC_SCRATCH_BYTES (16ll << 20)
+int pjds_spmv_noalloc(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                      const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+                      const int32_t *d_sched, int32_t dtype, const void *d_x, void *d_y,
+                      uint32_t flags, void *stream);
+
+/*
  * y = alpha (A x) + beta z, the product with a fused update (pjds_spmv's arguments plus
  * alpha, beta and d_z; d_z NULL means beta is ignored).  z is indexed like y (permuted order
  * with PJDS_Y_PERMUTED, original order otherwise) and may be y itself, which accumulates:

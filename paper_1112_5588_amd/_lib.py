@@ -33,6 +33,7 @@ PJDS_Y_PERMUTED = 0x4
 PJDS_XCD_REMAP = 0x8
 PJDS_TWO_ROWS = 0x10
 PJDS_LANES_SHIFT = 8
+PJDS_NOALLOC_SCRATCH_BYTES = 16 << 20
 PJDS_LANES_MASK = 0x7 << PJDS_LANES_SHIFT
 
 
@@ -87,6 +88,7 @@ _SIGS = {
     "pjds_workspace_size": [_ip, _i32, ctypes.POINTER(ctypes.c_int64)],
     "pjds_workspace_init": [_ip, _i32, _vp, _vp],
     "pjds_spmv": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
+    "pjds_spmv_noalloc": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmmv": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _u32, _vp],
     "pjds_spmmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "pjds_spmv_axpby": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _u32, _vp],
@@ -304,6 +306,18 @@ def pjds_spmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d
                            _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dev(d_work),
                            _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y), flags, _stream(stream)),
            "pjds_spmv")
+
+
+def pjds_spmv_noalloc(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched,
+                      d_x, d_y, flags: int = 0, stream=None) -> None:
+    """pjds_spmv without a workspace argument: the library's fixed device scratch holds the
+    long-row partial sums (calls that overlap on one GPU race)."""
+    _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
+                   need_perm=not flags & PJDS_Y_PERMUTED)
+    _dev_int(d_sched, 4 * info.n_chunks, np.int32, "sched", like=d_y, required=info.n_chunks > 0)
+    _check(lib().pjds_spmv_noalloc(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
+                                   _dev(d_val_p), _dev(d_perm), _dev(d_sched), _dtype_code(d_y.dtype),
+                                   _dev(d_x), _dev(d_y), flags, _stream(stream)), "pjds_spmv_noalloc")
 
 
 def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "device.h"
 #include "launch.h"
@@ -1040,6 +1041,35 @@ void launch_spmv_epi(const pjds_info &in, const int32_t *d_row_len, const int64_
     launch_product(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, d_sched, d_work, dtype, d_x, d_y, ea, flags, s);
 }
 
+// ---- fixed device scratch of pjds_spmv_noalloc -----------------------------------------
+// The long-row partial sums and completion counters of that entry point live here, in the
+// code object's own device memory, so the call allocates nothing.  In host code `scratch` only
+// names the variable: its device address, different on each GPU, comes from
+// hipGetSymbolAddress with that GPU current, and only that address goes to kernels.
+static __device__ __align__(256) unsigned char scratch[PJDS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+int scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PJDS_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PJDS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PJDS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PJDS_OK;
+}
+
 }  // namespace pjds
 
 using namespace pjds;
@@ -1081,6 +1111,41 @@ int pjds_spmv(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_
     launch_product(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, d_work, dtype, d_x, d_y,
                    EpiArgs{}, flags, static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv");
+}
+
+int pjds_spmv_noalloc(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
+                      const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm,
+                      const int32_t *d_sched, int32_t dtype, const void *d_x, void *d_y,
+                      uint32_t flags, void *stream) {
+    if (int rc = check_info(info, dtype)) return rc;
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP | PJDS_TWO_ROWS))
+        return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
+    if (flags & PJDS_TWO_ROWS)
+        if (int rc = check_two_rows(*info)) return rc;
+    const int64_t partial_bytes = ws_partials_bytes(*info, dtype);
+    const int64_t need = info->n_chunks ? partial_bytes + (info->n_chunks * 4 + 255) / 256 * 256 : 0;
+    if (need > PJDS_NOALLOC_SCRATCH_BYTES)
+        return fail(PJDS_ERR_OVERFLOW, "long-row workspace of %lld bytes exceeds the fixed scratch of %lld bytes",
+                    (long long)need, (long long)PJDS_NOALLOC_SCRATCH_BYTES);
+    if (info->n_rows == 0) return PJDS_OK;
+    if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (info->nnz_stored && (!d_col_p || !d_val_p || !d_x)) return fail(PJDS_ERR_ARG, "NULL device array");
+    if (!(flags & PJDS_Y_PERMUTED) && !d_perm) return fail(PJDS_ERR_ARG, "d_perm is NULL (needed to scatter y)");
+    if (info->n_chunks && !d_sched) return fail(PJDS_ERR_ARG, "long rows need d_sched");
+    void *work = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (info->n_chunks) {
+        if (int rc = scratch_address(&work)) return rc;
+        // the counters must start at zero whatever an earlier call left behind
+        int32_t *counters = reinterpret_cast<int32_t *>(static_cast<char *>(work) + partial_bytes);
+        const int64_t n = info->n_chunks;
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(unsigned(std::min<int64_t>(ceil_div(n, kBlock), 1024))), dim3(kBlock), 0,
+                           s, counters, n);
+        if (int rc = launch_status("pjds_spmv_noalloc (clearing counters)")) return rc;
+    }
+    launch_product(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_sched, work, dtype, d_x, d_y,
+                   EpiArgs{}, flags, s);
+    return launch_status("pjds_spmv_noalloc");
 }
 
 int pjds_spmv_axpby(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,

@@ -158,6 +158,28 @@ def test_device_entry_points_validate_before_touching_the_gpu():
     assert lib.pjds_probe(3, None, None, 10, None) == L.PJDS_ERR_ARG
 
 
+def test_noalloc_product_refuses_plans_beyond_its_fixed_scratch():
+    """pjds_spmv_noalloc takes the long-row workspace from a fixed 16 MiB array: a plan that
+    needs more is refused with an overflow status before anything reaches the GPU (only the
+    row pointers are needed to plan)."""
+    n, length = 1 << 18, 256
+    row_ptr = np.arange(n + 1, dtype=np.int64) * length
+    info = L.pjds_plan(n, n, row_ptr, 64, 0, L.PJDS_LAYOUT_JD, 8)
+    need = L.pjds_workspace_size(info, np.float64)
+    assert need > L.PJDS_NOALLOC_SCRATCH_BYTES
+    lib = L.lib()
+    rc = lib.pjds_spmv_noalloc(ctypes.byref(info), None, None, None, None, None, None, 0, None, None, 0, None)
+    assert rc == L.PJDS_ERR_OVERFLOW
+    assert "scratch" in L.pjds_last_error()
+    # a plan within the limit passes the size check and fails on the NULL arrays instead
+    small = L.pjds_plan(4096, 4096, np.arange(4097, dtype=np.int64) * length, 64, 0, L.PJDS_LAYOUT_JD, 64)
+    assert 0 < L.pjds_workspace_size(small, np.float64) <= L.PJDS_NOALLOC_SCRATCH_BYTES
+    assert lib.pjds_spmv_noalloc(ctypes.byref(small), None, None, None, None, None, None, 0, None, None, 0,
+                                 None) == L.PJDS_ERR_ARG
+    assert lib.pjds_spmv_noalloc(ctypes.byref(small), None, None, None, None, None, None, 0, None, None, 0x100,
+                                 None) == L.PJDS_ERR_ARG
+
+
 def test_lanes_matrix_is_refused_by_the_products_that_do_not_take_it():
     A = synth.random_csr(500, 500, 3, max_len=30)
     info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 16, 128, L.PJDS_LAYOUT_BLOCK | L.PJDS_LANES(2), 0)

@@ -439,9 +439,9 @@ int mlp_infer(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch,
               float *d_margin, void *stream);
 
 /* ---- measurement helpers ------------------------------------------------------------ */
-/* Stream probes for the achievable bandwidth ceiling, 16-byte loads with several in flight per
- * thread.  mode 0 reads n doubles with non-temporal loads and writes one partial sum per
- * workgroup to d_out (at most 2048 values), mode 1 copies n doubles d_in -> d_out, mode 2
+/* Stream probes for the achievable bandwidth ceiling: each workgroup streams a contiguous chunk
+ * with 16-byte loads, several in flight per thread.  mode 0 reads n doubles with non-temporal
+ * loads and writes one partial sum per workgroup to d_out (1024 values), mode 1 copies n doubles d_in -> d_out, mode 2
  * reads like mode 0 with ordinary cached loads: a read-only pass that evicts what the caches
  * (the Infinity Cache included) held before, leaving no dirty line to write back.  d_in and
  * d_out are device arrays of n doubles (mode 1) or of n and 2048 doubles (modes 0, 2). */

@@ -38,6 +38,15 @@ struct EpiArgs {
     // permuted): workgroup t of the product writes sum over its rows i of y_i * x_i to
     // dot_partial[t], in a fixed order (binary64)
     double *dot_partial = nullptr;
+    // if set (the same staged two-rows product, as a Lanczos step): every workgroup adds the
+    // n_norm values norm_part[] in a fixed order into t, and the epilogue uses alpha = 1 / b and
+    // beta = -b * inv_prev[0] (beta only when z is set) with b = sqrt(t); the workgroup of the
+    // first tile writes inv_out[0] = 1 / b and, if beta_out is set, beta_out[0] = b
+    const double *norm_part = nullptr;
+    int32_t n_norm = 0;
+    const double *inv_prev = nullptr;
+    double *inv_out = nullptr;
+    double *beta_out = nullptr;
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

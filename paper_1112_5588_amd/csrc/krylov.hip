@@ -12,17 +12,21 @@
 //     alpha_j = (w . u_j) / s_j                       deterministic two-stage reduction; with
 //                                                     x staged in LDS the product's workgroups
 //                                                     sum w_i u_j[i] over their own rows (u_j[i]
-//                                                     is staged) and one small kernel adds the
-//                                                     partial sums
-//     w = w - (alpha_j / s_j) u_j;  t = w . w         one pass
-//     beta_{j+1} = sqrt(t);  u_{j+1} = w
+//                                                     is staged), and every workgroup of the
+//                                                     update adds those partial sums itself
+//     w = w - (alpha_j / s_j) u_j;  t = w . w         one pass (the update)
+//     beta_{j+1} = sqrt(t);  u_{j+1} = w              with x staged: added up by every
+//                                                     workgroup of the next product, before
+//                                                     its epilogue needs 1 / s_{j+1}
 //
-// Every scalar stays in device memory and every kernel reads it there, so a step needs no
+// Every scalar stays in device memory or is recomputed where it is needed, so a step needs no
 // host synchronisation and a sequence of steps can be captured in a graph.  Reductions use a
-// fixed grid and fixed summation trees: results are reproducible bit for bit.  Vector passes
-// per step besides the product's own x and y traffic: four with x staged in LDS (z read; w
-// and u_j read and w written by the update), six with x through the caches (w and u_j read
-// once more for alpha).
+// fixed grid and fixed summation trees, and a workgroup that adds another kernel's partial sums
+// adds them in the same order as every other: results are reproducible bit for bit, with no
+// device-scope fence or atomic.  With x staged in LDS a step is two kernels, the product and the
+// update; vector passes per step besides the product's own x and y traffic: four (z read; w and
+// u_j read and w written by the update), six with x through the caches (w and u_j read once
+// more for alpha, in a kernel of its own, and two small kernels finish the scalars).
 #include <algorithm>
 #include <cmath>
 
@@ -56,25 +60,60 @@ __global__ __launch_bounds__(kRedThreads) void dot_partial_kernel(int64_t n, con
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// w = w - (*alpha) (*scale) v, and partial[b] = this block's share of w . w (new w)
-__global__ __launch_bounds__(kRedThreads) void axpy_norm_partial_kernel(int64_t n, double *__restrict__ w,
-                                                                        const double *__restrict__ v,
-                                                                        const double *__restrict__ alpha,
-                                                                        const double *__restrict__ scale,
-                                                                        double *__restrict__ partial) {
-    __shared__ double red[kRedThreads];
-    const double a = alpha[0] * scale[0];
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * int64_t(kRedThreads) + threadIdx.x; i < n; i += int64_t(kRedBlocks) * kRedThreads) {
-        const double wi = __builtin_fma(-a, v[i], w[i]);
-        w[i] = wi;
-        s = __builtin_fma(wi, wi, s);
+// The update pass: alpha_j = (sum of the n_dot partials dot_part[] in a fixed order) * inv_s[0],
+// added up by every workgroup (the same bits everywhere; workgroup 0 stores it in alpha_out[0]);
+// then w = w - alpha_j inv_s[0] v and partial[b] = this workgroup's share of w . w (new w), each
+// thread taking kUpdInFlight elements per round with all loads issued first.
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdBlocks = 512;     // fixed, so the summation order never depends on the device
+constexpr int kUpdInFlight = 4;
+__device__ __forceinline__ double block_sum_upd(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kUpdThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
     }
-    const double t = block_sum(s, red);
+    return red[0];
+}
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *__restrict__ w,
+                                                             const double *__restrict__ v,
+                                                             const double *__restrict__ dot_part, int64_t n_dot,
+                                                             const double *__restrict__ inv_s,
+                                                             double *__restrict__ alpha_out,
+                                                             double *__restrict__ partial) {
+    __shared__ double red[kUpdThreads];
+    double d = 0.0;
+    for (int64_t q = threadIdx.x; q < n_dot; q += kUpdThreads) d += dot_part[q];
+    const double alpha = block_sum_upd(d, red) * inv_s[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[0] = alpha;
+    const double a = alpha * inv_s[0];
+    const int64_t stride = int64_t(kUpdBlocks) * kUpdThreads;
+    double s = 0.0;
+    for (int64_t i0 = blockIdx.x * int64_t(kUpdThreads) + threadIdx.x; i0 < n; i0 += stride * kUpdInFlight) {
+        double wv[kUpdInFlight], vv[kUpdInFlight];
+#pragma unroll
+        for (int u = 0; u < kUpdInFlight; ++u) {
+            const int64_t i = i0 + u * stride;
+            wv[u] = i < n ? w[i] : 0.0;
+            vv[u] = i < n ? v[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUpdInFlight; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < n) {
+                const double wi = __builtin_fma(-a, vv[u], wv[u]);
+                w[i] = wi;
+                s = __builtin_fma(wi, wi, s);
+            }
+        }
+    }
+    __syncthreads();                                        // red[] is reused
+    const double t = block_sum_upd(s, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// Sum of the kRedBlocks partials (fixed tree), then one of
+// Sum of n_part partials (fixed tree), then one of
 //   kAlpha:  out[0] = sum * inv_s[0]                           (alpha_j = (w . u_j) / s_j)
 //   kBeta:   b = sqrt(sum); out[0] = b; inv_next[0] = 1 / b;   (beta_{j+1}, 1 / s_{j+1},
 //            zc_next[0] = b * inv_s[0]                          beta_{j+1} / s_j)
@@ -93,16 +132,17 @@ __global__ __launch_bounds__(kRedThreads) void finish_kernel(const double *__res
     } else if (mode == kBeta) {
         const double b = sqrt(t);
         out[0] = b;
-        inv_next[0] = 1.0 / b;
-        zc_next[0] = b * inv_s[0];
+        if (inv_next) inv_next[0] = 1.0 / b;
+        if (zc_next) zc_next[0] = b * inv_s[0];
     } else {
         inv_next[0] = 1.0 / sqrt(t);
     }
 }
 
-// Partial sums a step can leave: the reduction grid's, or one per row tile of the staged
-// product (tiles of at least 256 rows).
-int64_t partial_slots(const pjds_info &in) { return std::max<int64_t>(kRedBlocks, ceil_div(in.n_pad, 256)); }
+// Partial sums a step leaves: w . u_j (the reduction grid's, or one per row tile of the staged
+// product, tiles of at least 256 rows), then w . w (the update's) in a region of its own.
+int64_t dot_slots(const pjds_info &in) { return std::max<int64_t>(kRedBlocks, ceil_div(in.n_pad, 256)); }
+int64_t partial_slots(const pjds_info &in) { return dot_slots(in) + std::max(kRedBlocks, kUpdBlocks); }
 
 __global__ void fill_kernel(int64_t n, double *p, double v) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
@@ -144,13 +184,17 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     double *V = static_cast<double *>(d_vectors);
     double *part = static_cast<double *>(d_scratch);
-    // device scalars, two slots each (step j reads slot j % 2, its last kernel writes the other)
-    double *inv_s = part + partial_slots(in);   // 1 / s_j
-    double *zc = inv_s + 2;                     // beta_j / s_{j-1}
-    // 1 / s_0 = 1 / |v|, beta_0 = 0
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int64_t(kRedBlocks), int(kNorm), nullptr,
-                       nullptr, inv_s, nullptr);
+    double *part_dot = part;                        // w . u_j partials
+    double *part_nrm = part + dot_slots(in);        // w . w partials (and v . v before step 0)
+    // device scalars, two slots each (step j reads slot j % 2 and writes the other)
+    double *inv_s = part + partial_slots(in);       // 1 / s_j
+    double *zc = inv_s + 2;                         // beta_j / s_{j-1} (x through the caches)
+    const bool staged = x_halo >= 0;
+    // |v|^2 as partial sums (the staged product's first step adds them itself); beta_0 = 0
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part_nrm);
+    if (!staged)
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part_nrm, int64_t(kRedBlocks), int(kNorm),
+                           nullptr, nullptr, inv_s, nullptr);
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, int64_t(1), d_beta, 0.0);
     for (int32_t j = 0; j < steps; ++j) {
         // u_0 is the caller's v (read only); then w of step j lands in V[(j + 1) % 3], which
@@ -161,28 +205,37 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
         double *inv_j = inv_s + (j & 1), *inv_n = inv_s + ((j + 1) & 1);
         // w = (1/s_j) A u_j - (beta_j / s_{j-1}) u_{j-1}
         EpiArgs ea;
-        ea.alpha_dev = inv_j;
         ea.z = uprev;
-        ea.beta_dev = zc + (j & 1);
-        ea.bscale = -1.0;
-        int64_t n_part = kRedBlocks;
-        if (x_halo >= 0) {
-            // w . u_j as per-tile partial sums in the product's epilogue
-            ea.dot_partial = part;
-            n_part = xlds_tiles(in, tile_rows);
+        int64_t n_dot = kRedBlocks;
+        if (staged) {
+            // 1 / s_j and beta_j / s_{j-1} from the partials of |u_j|^2 in every workgroup;
+            // w . u_j as per-tile partial sums in the epilogue
+            ea.norm_part = part_nrm;
+            ea.n_norm = j == 0 ? kRedBlocks : kUpdBlocks;
+            ea.inv_prev = j == 0 ? nullptr : inv_n;     // slot (j - 1) % 2 = (j + 1) % 2
+            ea.inv_out = inv_j;
+            ea.beta_out = j == 0 ? nullptr : d_beta + j;
+            ea.dot_partial = part_dot;
+            n_dot = xlds_tiles(in, tile_rows);
             launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, uj, w, x_halo, tile_rows, ea,
                         PJDS_Y_PERMUTED | PJDS_TWO_ROWS, s);
         } else {
+            ea.alpha_dev = inv_j;
+            ea.beta_dev = zc + (j & 1);
+            ea.bscale = -1.0;
             launch_spmv_epi(in, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, PJDS_F64, uj, w, ea,
                             PJDS_Y_PERMUTED, s);
-            hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part);
+            hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part_dot);
         }
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, n_part, int(kAlpha), inv_j,
-                           d_alpha + j, nullptr, nullptr);
-        hipLaunchKernelGGL(axpy_norm_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, d_alpha + j,
-                           inv_j, part);
-        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part, int64_t(kRedBlocks), int(kBeta), inv_j,
-                           d_beta + j + 1, inv_n, zc + ((j + 1) & 1));
+        // alpha_j, then w -= (alpha_j / s_j) u_j with the partials of |w|^2
+        hipLaunchKernelGGL(update_kernel, dim3(kUpdBlocks), dim3(kUpdThreads), 0, s, n, w, uj, part_dot, n_dot, inv_j,
+                           d_alpha + j, part_nrm);
+        // beta_{j+1}: the next staged product adds the partials itself; otherwise, and after
+        // the last step, one small kernel
+        if (!staged || j == steps - 1)
+            hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kRedThreads), 0, s, part_nrm, int64_t(kUpdBlocks),
+                               int(kBeta), inv_j, d_beta + j + 1, staged ? nullptr : inv_n,
+                               staged ? nullptr : zc + ((j + 1) & 1));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(PJDS_ERR_HIP, "pjds_lanczos: %s", hipGetErrorString(e));

@@ -143,6 +143,11 @@ struct Epilogue {
     T bscale;
     const T *alpha_dev;                 // if set, alpha = *alpha_dev
     double *dot;                        // if set, per-workgroup sums of y_i * x_i (staged products)
+    const double *norm_part;            // if set, a Lanczos step's scalars come from these
+    int32_t n_norm;                     // partial sums (EpiArgs)
+    const double *inv_prev;
+    double *inv_out;
+    double *beta_out;
     __device__ T operator()(T acc, int64_t r) const {
         const T a = alpha_dev ? alpha_dev[0] : alpha;
         if (!z) return a * acc;
@@ -521,6 +526,11 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
     int64_t i = r0 + R * int64_t(threadIdx.x);
     I lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
     int64_t base = addr.base(i < n_pad ? i : n_pad - R);
+    // a Lanczos step: this thread's share of the previous pass's partial sums, loaded with the
+    // copy of x and added up after it
+    double npart = 0.0;
+    if (epi.norm_part)
+        for (int q = threadIdx.x; q < epi.n_norm; q += NT) npart += epi.norm_part[q];
     for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
         T v[kStage];
 #pragma unroll
@@ -534,7 +544,30 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
             if (c < hi) xs[c - lo] = v[u];
         }
     }
-    __syncthreads();
+    __shared__ double wsum[NT / kWave];
+    Epilogue<T> ep = epi;
+    if (epi.norm_part) {
+        // the same fixed-order sum in every workgroup: butterfly inside each wave, then the
+        // waves in order; b = sqrt(sum) is beta_j (the norm of the Lanczos vector u_j)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) npart += __shfl_xor(npart, off);
+        if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = npart;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < NT / kWave; ++w) t += wsum[w];
+        const double b = sqrt(t), inv = 1.0 / b;
+        ep.alpha = T(inv);
+        ep.alpha_dev = nullptr;
+        if (epi.z) {
+            ep.beta = T(-(b * epi.inv_prev[0]));
+            ep.beta_dev = nullptr;
+        }
+        if (r0 == 0 && threadIdx.x == 0) {
+            epi.inv_out[0] = inv;
+            if (epi.beta_out) epi.beta_out[0] = b;
+        }
+    }
+    __syncthreads();                    // x staged; wsum free again
     const XStaged<T> xr{x, xs, lo, uint32_t(hi > lo ? hi - lo : 0)};
     const bool y_perm = flags & PJDS_Y_PERMUTED;
     double dsum = 0.0;                  // this thread's rows' y_i * x_i (epi.dot only)
@@ -549,8 +582,8 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
         for (int q = 0; q < R; ++q)
             if (i + q < n_rows) {
                 const int64_t r = y_perm ? i + q : perm[i + q];
-                const T v = epi(acc[q], r);
-                epi.put(y, r, v);
+                const T v = ep(acc[q], r);
+                ep.put(y, r, v);
                 // a square matrix in the permuted basis: row i's own entry of x is staged
                 if (epi.dot) dsum = __builtin_fma(double(v), double(xs[i + q - lo]), dsum);
             }
@@ -562,7 +595,6 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
     }
     if (epi.dot) {
         // fixed-order workgroup sum: butterfly inside each wave, then the waves in order
-        __shared__ double wsum[NT / kWave];
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off);
         if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = dsum;
@@ -727,27 +759,36 @@ __global__ __launch_bounds__(kBlock) void csr_vector_kernel(
 }
 
 // ---- bandwidth probes ---------------------------------------------------------------------
-// Streams of 16-byte loads, kProbeInFlight independent ones per thread and iteration, over a
-// grid of kProbeBlocks workgroups (8 per CU): enough requests in flight to find the ceiling
-// the memory system gives a streaming kernel.
+// Each workgroup streams its own contiguous chunk of the array with 16-byte loads,
+// kProbeInFlight independent ones per thread and round, over kProbeBlocks workgroups (four per
+// CU).  On an MI355X this layout read 2 GiB at 7.0 TB/s where a grid-strided one with four
+// loads in flight reached 6.0: the chunks keep every workgroup on its own DRAM pages.
 typedef double dbl2 __attribute__((ext_vector_type(2)));
-constexpr int kProbeInFlight = 4;
-constexpr int kProbeBlocks = 2048;
+constexpr int kProbeInFlight = 8;
+constexpr int kProbeBlocks = 1024;
+
+// [b0, b1): workgroup blockIdx.x's chunk of n2 16-byte elements
+__device__ __forceinline__ void probe_chunk(int64_t n2, int64_t &b0, int64_t &b1) {
+    const int64_t per = (n2 + gridDim.x - 1) / gridDim.x;
+    b0 = min(int64_t(blockIdx.x) * per, n2);
+    b1 = min(b0 + per, n2);
+}
 
 // Sum of n doubles, one partial sum per workgroup in out[blockIdx.x].  NT: non-temporal loads
 // (the read ceiling); else ordinary loads that allocate in every cache level on the way (a pass
 // that evicts what the caches held and leaves no dirty line behind).
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void probe_read_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
-    const int64_t n2 = n / 2, stride = int64_t(gridDim.x) * kBlock;
+    int64_t b0, b1;
+    probe_chunk(n / 2, b0, b1);
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
     dbl2 acc = {0.0, 0.0};
-    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += stride * kProbeInFlight) {
+    for (int64_t k = b0 + threadIdx.x; k < b1; k += int64_t(kBlock) * kProbeInFlight) {
         dbl2 v[kProbeInFlight];
 #pragma unroll
         for (int u = 0; u < kProbeInFlight; ++u) {
-            const int64_t e = k + u * stride;
-            v[u] = e < n2 ? (NT ? __builtin_nontemporal_load(in2 + e) : in2[e]) : dbl2{0.0, 0.0};
+            const int64_t e = k + u * kBlock;
+            v[u] = e < b1 ? (NT ? __builtin_nontemporal_load(in2 + e) : in2[e]) : dbl2{0.0, 0.0};
         }
 #pragma unroll
         for (int u = 0; u < kProbeInFlight; ++u) acc += v[u];
@@ -765,20 +806,21 @@ __global__ __launch_bounds__(kBlock) void probe_read_kernel(const double *__rest
 }
 
 __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t n) {
-    const int64_t n2 = n / 2, stride = int64_t(gridDim.x) * kBlock;
+    int64_t b0, b1;
+    probe_chunk(n / 2, b0, b1);
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
     dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
-    for (int64_t k = blockIdx.x * int64_t(kBlock) + threadIdx.x; k < n2; k += stride * kProbeInFlight) {
+    for (int64_t k = b0 + threadIdx.x; k < b1; k += int64_t(kBlock) * kProbeInFlight) {
         dbl2 v[kProbeInFlight];
 #pragma unroll
         for (int u = 0; u < kProbeInFlight; ++u) {
-            const int64_t e = k + u * stride;
-            v[u] = e < n2 ? __builtin_nontemporal_load(in2 + e) : dbl2{0.0, 0.0};
+            const int64_t e = k + u * kBlock;
+            v[u] = e < b1 ? __builtin_nontemporal_load(in2 + e) : dbl2{0.0, 0.0};
         }
 #pragma unroll
         for (int u = 0; u < kProbeInFlight; ++u) {
-            const int64_t e = k + u * stride;
-            if (e < n2) __builtin_nontemporal_store(v[u], out2 + e);
+            const int64_t e = k + u * kBlock;
+            if (e < b1) __builtin_nontemporal_store(v[u], out2 + e);
         }
     }
     if (n & 1 && blockIdx.x == 0 && threadIdx.x == 0) out[n - 1] = in[n - 1];
@@ -787,7 +829,8 @@ __global__ __launch_bounds__(kBlock) void probe_copy_kernel(const double *__rest
 template <class T>
 Epilogue<T> make_epi(const EpiArgs &a) {
     return Epilogue<T>{T(a.alpha), T(a.beta), static_cast<const T *>(a.z), static_cast<const T *>(a.beta_dev),
-                       T(a.bscale), static_cast<const T *>(a.alpha_dev), a.dot_partial};
+                       T(a.bscale), static_cast<const T *>(a.alpha_dev), a.dot_partial, a.norm_part,
+                       a.n_norm, a.inv_prev, a.inv_out, a.beta_out};
 }
 
 int launch_status(const char *what) {
@@ -1263,7 +1306,7 @@ int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int
 int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream) {
     if ((mode != 0 && mode != 1 && mode != 2) || n < 0 || !d_in || !d_out) return fail(PJDS_ERR_ARG, "bad probe arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid(unsigned(std::min<int64_t>(std::max<int64_t>(ceil_div(n / 2, kBlock * kProbeInFlight), 1), kProbeBlocks)));
+    const dim3 grid(static_cast<unsigned>(kProbeBlocks));
     if (mode == 0) hipLaunchKernelGGL(probe_read_kernel<true>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
     else if (mode == 2) hipLaunchKernelGGL(probe_read_kernel<false>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
     else hipLaunchKernelGGL(probe_copy_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);

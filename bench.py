@@ -5,7 +5,7 @@ Default workload: the Holstein-Hubbard-like matrix (N = 2^22 rows, banded symmet
 with contiguous off-diagonals, row lengths 5..20, N(0,1) values), FP64.  Default kernel
 configuration: the tuned pJDS form -- block height 64, rows sorted inside windows of 256
 (per-block layout), x staged in LDS per 1024-row tile with a halo of 768, two adjacent rows
-per lane, y written in the permuted basis (Listing 2).  The paper's plain configuration (global
+per lane, one-byte row lengths, y written in the permuted basis (Listing 2).  The paper's plain configuration (global
 sort, jagged-diagonal layout) is timed beside it in `extra.autotune`.
 
 One step is one product y = A x with the matrix and x already resident in HBM, run from a
@@ -440,6 +440,7 @@ def main() -> int:
                    "sort_window": M.info.sort_window, "xcd_remap": args.xcd_remap, "x_halo": args.x_halo,
                    "tile_rows": args.tile_rows if args.x_halo >= 0 else None,
                    "rows_per_lane": 2 if (args.x_halo >= 0 and args.two_rows) else 1,
+                   "row_lengths": "uint8" if (args.x_halo >= 0 and M.info.max_row_len <= 255) else "int32",
                    "split_len": M.info.split_len, "n_chunks": M.info.n_chunks,
                    "protocol": "median of the steps' product times, each product after a 1 GiB read-only pass with cached loads (Infinity Cache cold)"},
         "roofline": {"bound": "hbm", "achieved": round(gbs_mean, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -633,8 +634,9 @@ def main() -> int:
             torch.cuda.current_stream().wait_stream(cs)
             ms_g = time_launches(g.replay, 5, 1)
             ys = torch.empty(n, dtype=torch.float64, device="cuda")
+            # the product as the Lanczos step runs it (int32 row lengths)
             ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=args.x_halo, tile_rows=args.tile_rows,
-                                                      y_permuted=True, two_rows=True), 50, 5)
+                                                      y_permuted=True, two_rows=True, len8=False), 50, 5)
             # vector passes besides the product's x and y: z read, w and u_j read and w written by
             # the update; w and u_j read once more for alpha when x is not staged in LDS
             passes = 4 if args.x_halo >= 0 else 6

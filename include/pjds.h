@@ -66,6 +66,10 @@ extern "C" {
                                     long-row work items (ERR_UNSUPPORTED) and a global sort or a
                                     window that is a multiple of 128 (ERR_ARG); pjds_lanczos's
                                     LDS path uses it                                              */
+#define PJDS_ROW_LEN8      0x20u /* pjds_spmv_xlds: d_row_len points to n_pad one-byte lengths
+                                    (uint8_t, written by pjds_pack_lengths) instead of int32:
+                                    a quarter of the bytes, the same sums bit for bit; needs
+                                    max_row_len <= 255 (ERR_UNSUPPORTED)                         */
 /* Lanes per row (conversion flag, with PJDS_LAYOUT_BLOCK): PJDS_LANES(k) lets T = 2^k lanes
  * (k = 1..6) share each sorted row, the idea of the sliced ELLR-T format that the outlook of
  * Sect. 4 names beside pJDS.  The block height must then be b_r = 64 / T, so one block fills
@@ -228,6 +232,14 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
                    const int32_t *d_col_p, const void *d_val_p, const int32_t *d_perm, int32_t dtype,
                    const void *d_x, void *d_y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
                    void *stream);
+
+/*
+ * One-byte copies of the row lengths for the staged product's PJDS_ROW_LEN8 form:
+ * d_row_len8[i] = d_row_len[i] for i < n_pad (device arrays; d_row_len8 holds n_pad bytes).
+ * The lengths are the paper's rowmax array (Listing 2); at most 255 fits a byte, so a matrix
+ * with longer rows is refused with PJDS_ERR_UNSUPPORTED before anything is launched.
+ */
+int pjds_pack_lengths(const pjds_info *info, const int32_t *d_row_len, uint8_t *d_row_len8, void *stream);
 
 /*
  * Y = A X for k right-hand sides stored row-major (interleaved): X[c*k + v], Y[r*k + v]

@@ -32,6 +32,7 @@ PJDS_SYMMETRIC = 0x2
 PJDS_Y_PERMUTED = 0x4
 PJDS_XCD_REMAP = 0x8
 PJDS_TWO_ROWS = 0x10
+PJDS_ROW_LEN8 = 0x20
 PJDS_LANES_SHIFT = 8
 PJDS_NOALLOC_SCRATCH_BYTES = 16 << 20
 PJDS_LANES_MASK = 0x7 << PJDS_LANES_SHIFT
@@ -95,6 +96,7 @@ _SIGS = {
     "pjds_lanczos_workspace": [_ip, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
+    "pjds_pack_lengths": [_ip, _vp, _vp, _vp],
     "pjds_split_count": [_i64, _i64, _vp, _vp, _i64, _i64, ctypes.POINTER(_i64)],
     "pjds_split_columns": [_i64, _i64, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "ellr_plan": [_i64, _i64, _vp, _ip],
@@ -212,7 +214,7 @@ def _host_arr(a, n: int, dtype, name: str, required: bool = True):
 
 
 def _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y, k: int = 1,
-                   need_perm: bool = True):
+                   need_perm: bool = True, len8: bool = False):
     """The device operands of a product on a pJDS matrix, checked against its sizes: values
     and x, y of one type, x of n_cols * k and y of n_rows * k elements, index arrays of the
     planned lengths.  Returns the dtype code."""
@@ -223,7 +225,7 @@ def _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_
     _dev_vec(d_x, info.n_cols * k, code, "x", like=d_y)
     _dev_vec(d_val_p, info.nnz_stored, code, "val_p", like=d_y)
     _dev_int(d_col_p, info.nnz_stored, np.int32, "col_p", like=d_y)
-    _dev_int(d_row_len, info.n_pad, np.int32, "row_len", like=d_y)
+    _dev_int(d_row_len, info.n_pad, np.uint8 if len8 else np.int32, "row_len", like=d_y)
     _dev_int(d_offsets, info.n_offsets, np.int64, "offsets", like=d_y)
     _dev_int(d_perm, info.n_rows, np.int32, "perm", like=d_y, required=need_perm)
     return code
@@ -322,11 +324,20 @@ def pjds_spmv_noalloc(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d
 
 def pjds_spmv_xlds(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
                    x_halo: int, tile_rows: int = 0, flags: int = 0, stream=None) -> None:
+    """With PJDS_ROW_LEN8 in flags, d_row_len is the uint8 copy from pjds_pack_lengths."""
     _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, d_x, d_y,
-                   need_perm=not flags & PJDS_Y_PERMUTED)
+                   need_perm=not flags & PJDS_Y_PERMUTED, len8=bool(flags & PJDS_ROW_LEN8))
     _check(lib().pjds_spmv_xlds(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                                 _dev(d_val_p), _dev(d_perm), _dtype_code(d_y.dtype), _dev(d_x), _dev(d_y),
                                 x_halo, tile_rows, flags, _stream(stream)), "pjds_spmv_xlds")
+
+
+def pjds_pack_lengths(info: pjds_info, d_row_len, d_row_len8, stream=None) -> None:
+    """One-byte copies of the row lengths (d_row_len8: uint8 tensor of n_pad elements)."""
+    _dev_int(d_row_len, info.n_pad, np.int32, "row_len")
+    _dev_int(d_row_len8, info.n_pad, np.uint8, "row_len8", like=d_row_len)
+    _check(lib().pjds_pack_lengths(ctypes.byref(info), _dev(d_row_len), _dev(d_row_len8), _stream(stream)),
+           "pjds_pack_lengths")
 
 
 def pjds_spmmv(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, k: int,

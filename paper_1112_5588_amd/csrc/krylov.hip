@@ -63,18 +63,22 @@ __global__ __launch_bounds__(kRedThreads) void dot_partial_kernel(int64_t n, con
 // The update pass: alpha_j = (sum of the n_dot partials dot_part[] in a fixed order) * inv_s[0],
 // added up by every workgroup (the same bits everywhere; workgroup 0 stores it in alpha_out[0]);
 // then w = w - alpha_j inv_s[0] v and partial[b] = this workgroup's share of w . w (new w), each
-// thread taking kUpdInFlight elements per round with all loads issued first.
+// thread taking kUpdInFlight elements per round with all loads issued first.  The first
+// round's loads go out before the partials are added, so their latency overlaps that sum.
 constexpr int kUpdThreads = 1024;
 constexpr int kUpdBlocks = 512;     // fixed, so the summation order never depends on the device
 constexpr int kUpdInFlight = 4;
-__device__ __forceinline__ double block_sum_upd(double v, double *red) {
-    red[threadIdx.x] = v;
+// Sum over the workgroup in a fixed order: xor butterfly inside each wave, then the waves in
+// order (every thread returns the total).
+__device__ __forceinline__ double block_sum_upd(double v, double *wsum) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();                                        // wsum free
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
     __syncthreads();
-    for (int st = kUpdThreads / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    return red[0];
+    double t = 0.0;
+    for (int w = 0; w < kUpdThreads / kWave; ++w) t += wsum[w];
+    return t;
 }
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *__restrict__ w,
                                                              const double *__restrict__ v,
@@ -82,22 +86,26 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *
                                                              const double *__restrict__ inv_s,
                                                              double *__restrict__ alpha_out,
                                                              double *__restrict__ partial) {
-    __shared__ double red[kUpdThreads];
-    double d = 0.0;
-    for (int64_t q = threadIdx.x; q < n_dot; q += kUpdThreads) d += dot_part[q];
-    const double alpha = block_sum_upd(d, red) * inv_s[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[0] = alpha;
-    const double a = alpha * inv_s[0];
+    __shared__ double wsum[kUpdThreads / kWave];
     const int64_t stride = int64_t(kUpdBlocks) * kUpdThreads;
-    double s = 0.0;
-    for (int64_t i0 = blockIdx.x * int64_t(kUpdThreads) + threadIdx.x; i0 < n; i0 += stride * kUpdInFlight) {
-        double wv[kUpdInFlight], vv[kUpdInFlight];
+    int64_t i0 = blockIdx.x * int64_t(kUpdThreads) + threadIdx.x;
+    double wv[kUpdInFlight], vv[kUpdInFlight];
+    auto load = [&](int64_t b) {
 #pragma unroll
         for (int u = 0; u < kUpdInFlight; ++u) {
-            const int64_t i = i0 + u * stride;
+            const int64_t i = b + u * stride;
             wv[u] = i < n ? w[i] : 0.0;
             vv[u] = i < n ? v[i] : 0.0;
         }
+    };
+    load(i0);
+    double d = 0.0;
+    for (int64_t q = threadIdx.x; q < n_dot; q += kUpdThreads) d += dot_part[q];
+    const double alpha = block_sum_upd(d, wsum) * inv_s[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[0] = alpha;
+    const double a = alpha * inv_s[0];
+    double s = 0.0;
+    for (;;) {
 #pragma unroll
         for (int u = 0; u < kUpdInFlight; ++u) {
             const int64_t i = i0 + u * stride;
@@ -107,9 +115,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *
                 s = __builtin_fma(wi, wi, s);
             }
         }
+        i0 += stride * kUpdInFlight;
+        if (i0 >= n) break;
+        load(i0);
     }
-    __syncthreads();                                        // red[] is reused
-    const double t = block_sum_upd(s, red);
+    const double t = block_sum_upd(s, wsum);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "device.h"
 #include "launch.h"
@@ -278,7 +279,8 @@ __device__ __forceinline__ void row_group_sum(T (&acc)[R], int64_t base, int64_t
 // gathers, so the FMAs wait for the gathers only.  Every group is U steps wide; steps at or
 // past the wave's longest row m re-read step m - 1 (lines already fetched) and are masked,
 // so no load reaches past the longest row.  Same FMAs in the same order per row as
-// row_group_sum.
+// row_group_sum.  The caller loads the first group (steps [0, U)) into ga, so it can issue
+// those loads early, before work that does not depend on them.
 template <int U, int R, class T>
 struct StepGroup {
     typedef typename VecR<T, R>::type V;
@@ -317,7 +319,7 @@ struct StepGroup {
 };
 
 template <int R, class T, class Addr, class XR>
-__device__ __forceinline__ void row_group_sum_pipe(T (&acc)[R], int64_t base, int64_t base_lead, const int (&len)[R],
+__device__ __forceinline__ void row_group_sum_pipe(T (&acc)[R], StepGroup<(R >= 4 ? 2 : 4), R, T> &ga, int64_t base, int64_t base_lead, const int (&len)[R],
                                                    int m, const Addr &addr, const int32_t *__restrict__ col_p,
                                                    const T *__restrict__ val_p, const XR &xr) {
     constexpr int U = R >= 4 ? 2 : 4;
@@ -325,7 +327,7 @@ __device__ __forceinline__ void row_group_sum_pipe(T (&acc)[R], int64_t base, in
     for (int q = 0; q < R; ++q) acc[q] = T(0);
     if (m <= 0) return;
     // two register sets in turn, so the loads in flight never have to land for a copy
-    StepGroup<U, R, T> ga, gb;
+    StepGroup<U, R, T> gb;
     auto step = [&](const StepGroup<U, R, T> &cur, StepGroup<U, R, T> &nxt, int jb) {
         T xv[U * R];
         cur.gather(xv, xr);
@@ -338,7 +340,6 @@ __device__ __forceinline__ void row_group_sum_pipe(T (&acc)[R], int64_t base, in
         cur.gather(xv, xr);
         cur.fma(acc, xv, jb, len);
     };
-    ga.load(0, m, len[0], base, base_lead, addr, col_p, val_p);
     const int groups = (m + U - 1) / U;
     int k = 1, jb = 0;
     for (; k + 1 < groups; k += 2, jb += 2 * U) {
@@ -441,6 +442,25 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv2_kernel(
         }
 }
 
+// Row lengths as the staged products read them: int32 (the converted rowmax array), or one
+// byte each (L8, PJDS_ROW_LEN8; the pointer then addresses uint8_t lengths).
+template <bool L8>
+__device__ __forceinline__ int row_len_at(const int32_t *rl, int64_t i) {
+    if (L8) return reinterpret_cast<const uint8_t *>(rl)[i];
+    return rl[i];
+}
+// The lengths of rows i and i + 1 (i even): one 8-byte or one 2-byte load.
+template <bool L8>
+__device__ __forceinline__ typename IdxR<2>::type row_len_pair(const int32_t *rl, int64_t i) {
+    typedef typename IdxR<2>::type I;
+    if (!L8) return *reinterpret_cast<const I *>(rl + i);
+    const uint16_t p = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(rl) + i);
+    I r;
+    r[0] = p & 0xff;
+    r[1] = p >> 8;
+    return r;
+}
+
 // pJDS product with the right-hand side staged in LDS (block layout with a sort window).
 // A workgroup of NT threads (256 or 512) owns `tile` consecutive sorted rows (a multiple of
 // 256; NT = 512 when the tile is a multiple of 512, so a 512-row tile runs in one pass).
@@ -449,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv2_kernel(
 // LDS once with coalesced loads, then runs its rows NT at a time; entries whose column falls
 // in the staged range read x from LDS, the others from global memory.  Rows are never split
 // here.  Same arithmetic order as pjds_spmv_kernel.
-template <class T, int BR, int NT>
+template <class T, int BR, int NT, bool L8>
 __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
     int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
@@ -467,7 +487,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
     // address the last real row, so the offsets are never read out of range.
     const PjdsAddr<false, BR> addr{offsets};
     int64_t i = r0 + threadIdx.x;
-    int len = i < n_pad ? row_len[i] : 0;
+    int len = i < n_pad ? row_len_at<L8>(row_len, i) : 0;
     int64_t base = addr.base(i < n_pad ? i : n_pad - 1);
     // copy x[lo, hi) with kStage independent loads in flight per thread
     for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
@@ -496,7 +516,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
         rb += NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
         i = rb + threadIdx.x;
-        len = i < n_pad ? row_len[i] : 0;
+        len = i < n_pad ? row_len_at<L8>(row_len, i) : 0;
         base = addr.base(i < n_pad ? i : n_pad - 1);
     }
 }
@@ -505,8 +525,8 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
 // threads run R NT rows per pass; a wave covers 64 R sorted rows, so the sort window must
 // hold whole groups of that size (their longest row is lane 0's first).  Same staging as
 // above; each row's sum is the same FMAs in the same order as pjds_spmv_kernel.
-template <class T, int BR, int NT>
-__global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
+template <class T, int BR, int NT, bool L8>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void pjds_spmv_lds2_kernel(
     int64_t n_rows, int64_t n_cols, int64_t n_pad, int64_t window, int64_t halo, int64_t tile,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
     const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
@@ -524,14 +544,38 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
     // n_pad is a multiple of R, so a group never straddles it; groups past it address the
     // last real group
     int64_t i = r0 + R * int64_t(threadIdx.x);
-    I lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+    I lv = i < n_pad ? row_len_pair<L8>(row_len, i) : I{};
     int64_t base = addr.base(i < n_pad ? i : n_pad - R);
     // a Lanczos step: this thread's share of the previous pass's partial sums, loaded with the
     // copy of x and added up after it
     double npart = 0.0;
-    if (epi.norm_part)
-        for (int q = threadIdx.x; q < epi.n_norm; q += NT) npart += epi.norm_part[q];
-    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
+    if (epi.norm_part) {
+        npart = int(threadIdx.x) < epi.n_norm ? epi.norm_part[threadIdx.x] : 0.0;   // no wait here
+        for (int q = threadIdx.x + NT; q < epi.n_norm; q += NT) npart += epi.norm_part[q];
+    }
+    // the first chunk of x to stage, then the first group of matrix steps of the first pass
+    // (it needs only the lengths and offsets), then the copy into LDS: those matrix loads are
+    // in flight across the copy and the barrier
+    T sv[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+        const int64_t c = lo + threadIdx.x + int64_t(u) * NT;
+        sv[u] = c < hi ? x[c] : T(0);
+    }
+    StepGroup<(R >= 4 ? 2 : 4), R, T> g0;
+    int len0[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) len0[q] = lv[q];
+    const int m0 = wave_first(len0[0]);
+    const int64_t bl0 = wave_first(base);
+    if (m0 > 0) g0.load(0, m0, len0[0], base, bl0, addr, col_p, val_p);
+    __builtin_amdgcn_sched_barrier(0);      // keep those loads ahead of the LDS writes
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+        const int64_t c = lo + threadIdx.x + int64_t(u) * NT;
+        if (c < hi) xs[c - lo] = sv[u];
+    }
+    for (int64_t c0 = lo + threadIdx.x + int64_t(NT) * kStage; c0 < hi; c0 += int64_t(NT) * kStage) {
         T v[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
@@ -575,9 +619,15 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
         int len[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) len[q] = lv[q];
-        const int m = wave_first(len[0]);
         T acc[R];
-        row_group_sum_pipe<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, xr);
+        if (rb == r0) {
+            row_group_sum_pipe<R>(acc, g0, base, bl0, len0, m0, addr, col_p, val_p, xr);
+        } else {
+            const int m = wave_first(len[0]);
+            const int64_t bl = wave_first(base);
+            if (m > 0) g0.load(0, m, len[0], base, bl, addr, col_p, val_p);
+            row_group_sum_pipe<R>(acc, g0, base, bl, len, m, addr, col_p, val_p, xr);
+        }
 #pragma unroll
         for (int q = 0; q < R; ++q)
             if (i + q < n_rows) {
@@ -590,7 +640,7 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds2_kernel(
         rb += int64_t(R) * NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
         i = rb + R * int64_t(threadIdx.x);
-        lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+        lv = i < n_pad ? row_len_pair<L8>(row_len, i) : I{};
         base = addr.base(i < n_pad ? i : n_pad - R);
     }
     if (epi.dot) {
@@ -644,6 +694,11 @@ __global__ __launch_bounds__(kBlock) void pjds_lanes_kernel(
         const int64_t r = (flags & PJDS_Y_PERMUTED) ? i : perm[i];
         epi.store(y, r, acc);
     }
+}
+
+__global__ void pack_lengths_kernel(const int32_t *__restrict__ rl, uint8_t *__restrict__ rl8, int64_t n) {
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x)
+        rl8[k] = uint8_t(rl[k]);
 }
 
 __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
@@ -1039,12 +1094,13 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
     const bool two = flags & PJDS_TWO_ROWS;
     const int64_t per = two ? tile / kRowsPerLane : tile;     // threads the tile could use
     const int nt = two ? (per % 512 == 0 ? 512 : per % 256 == 0 ? 256 : 128) : tile % 512 == 0 ? 512 : kBlock;
-    auto go = [&](auto tag) {
+    auto go = [&](auto tag, auto l8) {
         using T = decltype(tag);
+        constexpr bool L8 = decltype(l8)::value;
         const int br = in.block_height;
         if (two) {
 #define PJDS_XLDS2_LAUNCH(B, N)                                                                           \
-            hipLaunchKernelGGL((pjds_spmv_lds2_kernel<T, B, N>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
+            hipLaunchKernelGGL((pjds_spmv_lds2_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
                                in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,              \
                                static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),          \
                                static_cast<T *>(d_y), make_epi<T>(ea), flags)
@@ -1060,7 +1116,7 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
             return;
         }
 #define PJDS_XLDS_LAUNCH(B, N)                                                                            \
-        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B, N>), grid, dim3(N), lds, s, in.n_rows, in.n_cols,     \
+        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
                            in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,                  \
                            static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
                            static_cast<T *>(d_y), make_epi<T>(ea), flags)
@@ -1073,8 +1129,14 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
 #undef PJDS_XLDS_CASE
 #undef PJDS_XLDS_LAUNCH
     };
-    if (dtype == PJDS_F64) go(double{});
-    else go(float{});
+    const bool len8 = flags & PJDS_ROW_LEN8;
+    if (dtype == PJDS_F64) {
+        if (len8) go(double{}, std::true_type{});
+        else go(double{}, std::false_type{});
+    } else {
+        if (len8) go(float{}, std::true_type{});
+        else go(float{}, std::false_type{});
+    }
 }
 
 void launch_spmv_epi(const pjds_info &in, const int32_t *d_row_len, const int64_t *d_offsets,
@@ -1243,9 +1305,11 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
                    const void *d_x, void *d_y, int32_t x_halo, int32_t tile_rows, uint32_t flags,
                    void *stream) {
     if (int rc = check_info(info, dtype)) return rc;
-    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP | PJDS_TWO_ROWS))
+    if (flags & ~(PJDS_Y_PERMUTED | PJDS_XCD_REMAP | PJDS_TWO_ROWS | PJDS_ROW_LEN8))
         return fail(PJDS_ERR_ARG, "unknown product flags 0x%x", flags);
     if (int rc = pjds::check_xlds(*info, dtype, x_halo, tile_rows)) return rc;
+    if ((flags & PJDS_ROW_LEN8) && info->max_row_len > 255)
+        return fail(PJDS_ERR_UNSUPPORTED, "PJDS_ROW_LEN8 with rows of %d entries (at most 255)", info->max_row_len);
     if (info->n_rows == 0) return PJDS_OK;
     if (!d_row_len || !d_offsets || !d_y) return fail(PJDS_ERR_ARG, "NULL device array");
     if (info->nnz_stored && (!d_col_p || !d_val_p)) return fail(PJDS_ERR_ARG, "NULL device array");
@@ -1255,6 +1319,19 @@ int pjds_spmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64_
     pjds::launch_xlds(*info, d_row_len, d_offsets, d_col_p, d_val_p, d_perm, dtype, d_x, d_y, x_halo, tile_rows,
                       EpiArgs{}, flags, static_cast<hipStream_t>(stream));
     return launch_status("pjds_spmv_xlds");
+}
+
+int pjds_pack_lengths(const pjds_info *info, const int32_t *d_row_len, uint8_t *d_row_len8, void *stream) {
+    if (!info) return fail(PJDS_ERR_ARG, "info is NULL");
+    if (info->n_pad < info->n_rows || info->n_rows < 0) return fail(PJDS_ERR_ARG, "inconsistent info");
+    if (info->max_row_len > 255)
+        return fail(PJDS_ERR_UNSUPPORTED, "rows of %d entries do not fit one byte", info->max_row_len);
+    if (info->n_pad == 0) return PJDS_OK;
+    if (!d_row_len || !d_row_len8) return fail(PJDS_ERR_ARG, "NULL device array");
+    const int64_t n = info->n_pad;
+    hipLaunchKernelGGL(pack_lengths_kernel, dim3(unsigned(std::min<int64_t>(ceil_div(n, kBlock), 4096))), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), d_row_len, d_row_len8, n);
+    return launch_status("pjds_pack_lengths");
 }
 
 int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_col_e,

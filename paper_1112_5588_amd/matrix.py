@@ -133,17 +133,36 @@ class PjdsMatrix:
                        alpha, beta, b["vectors"], b["scratch"], stream)
         return alpha[:steps], beta
 
+    def row_len8(self) -> torch.Tensor | None:
+        """The one-byte copy of the row lengths (made once, on first use), or None when a row
+        is longer than 255 entries."""
+        if self.info.max_row_len > 255:
+            return None
+        if "row_len8" not in self.d:
+            t = torch.empty(max(self.info.n_pad, 1), dtype=torch.uint8, device=self.device)
+            L.pjds_pack_lengths(self.info, self.d["row_len"], t)
+            self.d["row_len8"] = t
+        return self.d["row_len8"]
+
     def spmv_xlds(self, x: torch.Tensor, y: torch.Tensor | None = None, x_halo: int = 512,
                   tile_rows: int = 0, y_permuted: bool = False, xcd_remap: bool = False,
-                  stream=None, two_rows: bool = False) -> torch.Tensor:
+                  stream=None, two_rows: bool = False, len8: bool | None = None) -> torch.Tensor:
         """y = A x with x staged in LDS per workgroup tile (block layout, sort window % 256 == 0);
-        two_rows: each lane takes two adjacent rows with 2-wide loads."""
+        two_rows: each lane takes two adjacent rows with 2-wide loads; len8: read the one-byte
+        row lengths (None: whenever every row fits a byte)."""
         if y is None:
             y = torch.empty(self.info.n_rows, dtype=self.dtype, device=self.device)
         flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
         flags |= L.PJDS_TWO_ROWS if two_rows else 0
         d = self.d
-        L.pjds_spmv_xlds(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"], d["perm"], x, y,
+        rl = d["row_len"]
+        if len8 is None or len8:
+            r8 = self.row_len8()
+            if r8 is None and len8:
+                raise ValueError(f"rows of {self.info.max_row_len} entries do not fit one-byte lengths")
+            if r8 is not None:
+                rl, flags = r8, flags | L.PJDS_ROW_LEN8
+        L.pjds_spmv_xlds(self.info, rl, d["offsets"], d["col_p"], d["val_p"], d["perm"], x, y,
                          x_halo, tile_rows, flags, stream)
         return y
 

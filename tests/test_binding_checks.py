@@ -176,3 +176,33 @@ def test_c_staged_products_refuse_a_null_x_without_entries():
     rc = lib.pjds_spmmv_xlds(ctypes.byref(info), dummy, dummy, None, None, dummy, L.PJDS_F64, 4, 4, 4, None,
                              dummy, 256, 1024, L.PJDS_Y_PERMUTED, None)
     assert rc == L.PJDS_ERR_ARG and "d_X" in L.pjds_last_error()
+
+
+def test_one_byte_lengths_are_checked():
+    """With PJDS_ROW_LEN8 the lengths must be the uint8 copy (an int32 array there would be
+    read as bytes); pjds_pack_lengths wants an int32 source and a uint8 destination."""
+    B = synth.random_csr(3000, 3000, 5, max_len=12)
+    info = planned(B, sort_window=256, flags=L.PJDS_LAYOUT_BLOCK)
+    ops = operands(info)
+    with pytest.raises(TypeError):
+        L.pjds_spmv_xlds(info, ops["d_row_len"], ops["d_offsets"], ops["d_col_p"], ops["d_val_p"], ops["d_perm"],
+                         ops["d_x"], ops["d_y"], 256, 0, L.PJDS_ROW_LEN8)
+    with pytest.raises(TypeError):
+        L.pjds_pack_lengths(info, FakeDev(info.n_pad, torch.int32), FakeDev(info.n_pad, torch.int32))
+    with pytest.raises(ValueError):
+        L.pjds_pack_lengths(info, FakeDev(info.n_pad, torch.int32), FakeDev(info.n_pad - 1, torch.uint8))
+
+
+def test_one_byte_lengths_refused_for_long_rows_before_any_launch():
+    lens = np.ones(2000, np.int64)
+    lens[7] = 256
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    info = L.pjds_plan(2000, 2000, row_ptr, 64, 256, L.PJDS_LAYOUT_BLOCK, 0)
+    assert info.max_row_len == 256
+    lib = L.lib()
+    dummy = ctypes.c_void_p(16)
+    assert lib.pjds_pack_lengths(ctypes.byref(info), dummy, dummy, None) == L.PJDS_ERR_UNSUPPORTED
+    assert "byte" in L.pjds_last_error()
+    rc = lib.pjds_spmv_xlds(ctypes.byref(info), dummy, dummy, dummy, dummy, dummy, L.PJDS_F64, dummy, dummy,
+                            256, 0, L.PJDS_Y_PERMUTED | L.PJDS_ROW_LEN8, None)
+    assert rc == L.PJDS_ERR_UNSUPPORTED

@@ -457,3 +457,43 @@ def test_plain_two_rows_float32_and_refusals():
     with pytest.raises(L.PjdsError) as e:                   # a window of 64 rows
         PjdsMatrix.from_csr(A, layout="block", sort_window=64, split_len=-1).spmv(dev(x, torch.float32), two_rows=True)
     assert e.value.code == L.PJDS_ERR_ARG
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("two_rows,tile,halo,window", [(True, 1024, 768, 256), (True, 512, 256, 512),
+                                                       (False, 512, 512, 256), (False, 1024, 256, 1024)])
+def test_xlds_one_byte_lengths_give_the_same_bits(dtype, two_rows, tile, halo, window):
+    """PJDS_ROW_LEN8: the staged products read one-byte copies of the lengths and give the
+    same sums bit for bit; the copies are the lengths themselves."""
+    A = synth.hh_like(70001, seed=31)
+    A = A.astype(dtype) if dtype == np.float32 else A
+    x = synth.dense_x(A.n_cols, 31)
+    if dtype == np.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    M = PjdsMatrix.from_csr(A, layout="block", sort_window=window, keep_host=True)
+    r8 = M.row_len8()
+    assert r8 is not None and np.array_equal(host(r8)[:M.info.n_pad], M.host["row_len"].astype(np.uint8))
+    xd = dev(x, M.dtype)
+    y8 = M.spmv_xlds(xd, x_halo=halo, tile_rows=tile, y_permuted=True, two_rows=two_rows, len8=True)
+    y4 = M.spmv_xlds(xd, x_halo=halo, tile_rows=tile, y_permuted=True, two_rows=two_rows, len8=False)
+    assert torch.equal(y8, y4)
+    perm = M.host["perm"]
+    ys = np.empty_like(host(y8))
+    ys[perm] = host(y8)
+    assert_rows(ys, A, x, 8 if M.dtype == torch.float64 else 4)
+
+
+def test_xlds_one_byte_lengths_refused_for_long_rows():
+    # 1000 rows, the first of 300 entries: the lengths no longer fit a byte
+    lens = np.ones(1000, np.int64)
+    lens[0] = 300
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([np.arange(300), (np.arange(1, 1000) * 3) % 3000]).astype(np.int32)
+    B = synth.CSR(1000, 3000, rp, col, synth.uniform_pm1(32, 1, int(rp[-1])))
+    M = PjdsMatrix.from_csr(B, layout="block", sort_window=256)
+    assert M.row_len8() is None
+    xd = dev(synth.dense_x(3000, 32))
+    with pytest.raises(ValueError):
+        M.spmv_xlds(xd, len8=True)
+    y = M.spmv_xlds(xd)              # falls back to the int32 lengths
+    assert_rows(host(y), B, synth.dense_x(3000, 32))

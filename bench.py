@@ -3,7 +3,7 @@
 
 Default workload: the Holstein-Hubbard-like matrix (N = 2^22 rows, banded symmetric pattern
 with contiguous off-diagonals, row lengths 5..20, N(0,1) values), FP64.  Default kernel
-configuration: the tuned pJDS form -- block height 64, rows sorted inside windows of 256
+configuration: the tuned pJDS form -- block height 64, rows sorted inside windows of 512
 (per-block layout), x staged in LDS per 1024-row tile with a halo of 768, two adjacent rows
 per lane, one-byte row lengths, y written in the permuted basis (Listing 2).  The paper's plain configuration (global
 sort, jagged-diagonal layout) is timed beside it in `extra.autotune`.
@@ -301,7 +301,7 @@ def main() -> int:
     ap.add_argument("--layout", default="block", choices=["jd", "block"])
     ap.add_argument("--mode", default="y_permuted", choices=["y_permuted", "scatter", "symmetric"])
     ap.add_argument("--split-len", type=int, default=0)
-    ap.add_argument("--sort-window", type=int, default=256, help="0 = global sort")
+    ap.add_argument("--sort-window", type=int, default=512, help="0 = global sort")
     ap.add_argument("--xcd-remap", action="store_true")
     ap.add_argument("--x-halo", type=int, default=768,
                     help=">= 0: stage x in LDS with this halo (block layout, window % 256 == 0); -1: x through the caches")

@@ -318,9 +318,10 @@ def test_hh_like_full_size_sampled(hh_full, dtype):
     assert M.info.nnz_stored < E_info.nnz_stored
 
 
+@pytest.mark.parametrize("window", [512, 256])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_headline_configuration_full_size(hh_full, dtype):
-    # the benchmark's own launch: block layout, sort window 256, x staged in LDS with halo 768
+def test_headline_configuration_full_size(hh_full, dtype, window):
+    # the benchmark's own launch: block layout, sort window 512 (or 256), x staged in LDS with halo 768
     # and 1024-row tiles (4096 tiles, all in whole XCD groups), two rows per lane, y in the
     # permuted basis; sampled rows against the oracle, the whole vector bitwise against the
     # plain kernel and the one-row LDS form, and run-to-run reproducibility
@@ -328,7 +329,7 @@ def test_headline_configuration_full_size(hh_full, dtype):
     x = synth.dense_x(A.n_cols, 1)
     if dtype == np.float32:
         x = x.astype(np.float32).astype(np.float64)
-    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=256, keep_host=True)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=window, keep_host=True)
     xd = dev(x, M.dtype)
     yd = M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True)
     y = host(yd)
@@ -340,6 +341,8 @@ def test_headline_configuration_full_size(hh_full, dtype):
     assert torch.equal(yd, M.spmv(xd, y_permuted=True))
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=512, tile_rows=512, y_permuted=True))
     assert torch.equal(yd, M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True))
+    # the same launch with the int32 lengths
+    assert torch.equal(yd, M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True, len8=False))
 
 
 @pytest.mark.parametrize("k,t,tile", [(4, 4, 1024), (8, 8, 512)])

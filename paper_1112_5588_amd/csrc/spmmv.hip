@@ -9,6 +9,11 @@
 // 64 / LPR rows at a time exactly as pjds_spmmv does (LPR lanes per row, VPL contiguous vectors
 // per lane, the same FMAs in the same order), reading an X row from LDS when it was staged and
 // from global memory otherwise.  Results equal pjds_spmmv's bit for bit.
+//
+// Latency: the first group of matrix steps of a wave's first rows is loaded before X is
+// written into LDS (its loads are in flight across the copy and the barrier), and the row loop
+// keeps two register sets of matrix steps, loading the next group before the FMAs of the
+// current one, so a group's matrix loads overlap the previous group's gathers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,66 +51,102 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     const int64_t lo = max(lo_r - halo, int64_t(0));
     const int64_t hi = min(hi_r + halo, n_cols);
     const int32_t nr = int32_t(max(min(hi - lo, int64_t(cap)), int64_t(0)));   // staged X rows
-    // xs[r * TV + q] = X[(lo + r) * k + v0 + q]; vectors at or past k are staged as 0
-    const int32_t total = nr * TV;
-    for (int32_t e0 = 0; e0 < total; e0 += kThreads * kStage) {
-        T v[kStage];
-#pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int32_t e = e0 + u * kThreads + int32_t(threadIdx.x);
-            const int32_t r = e / TV, q = e % TV;
-            v[u] = e < total && v0 + q < k ? X[(lo + r) * k + v0 + q] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int32_t e = e0 + u * kThreads + int32_t(threadIdx.x);
-            if (e < total) xs[e] = v[u];
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     // this lane's first vector; k is a multiple of VPL, so a lane's VPL values are all inside
     // [0, k) or all outside (then it computes a copy of the last VPL vectors and stores nothing)
     const int v = v0 + (lane % LPR) * VPL;
     const int vc = v < k ? v : k - VPL;
     const int q0 = vc - v0;                        // offset of the lane's values in a staged row
-    for (int64_t rb = r0 + int64_t(threadIdx.x >> 6) * RW; rb < r1; rb += RP) {
-        const int64_t i = rb + lane / LPR;
-        const int len = i < n_pad ? row_len[i] : 0;
+    // the rows of a pass: lengths and offsets, then (after the copy's loads are out) the first
+    // group of matrix steps, in flight across the copy into LDS and the barrier
+    T av[2][U];
+    int32_t ac[2][U];
+    int64_t rb = r0 + int64_t(threadIdx.x >> 6) * RW;
+    int64_t i = rb + lane / LPR;
+    int len = i < n_pad ? row_len[i] : 0;
+    const int64_t ia0 = i < n_pad ? i : n_pad - 1;
+    int64_t base = offsets[ia0 / BR] + (ia0 % BR);
+    auto load_grp = [&](int jb, int m_, int64_t bl, T (&a_v)[U], int32_t (&a_c)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = jb + u < m_ ? jb + u : m_ - 1;     // uniform clamp past the longest row
+            const int64_t a = (j < len ? base : bl) + int64_t(j) * BR;
+            a_v[u] = ld_stream(val_p + a);
+            a_c[u] = ld_stream(col_p + a);
+        }
+    };
+    // xs[r * TV + q] = X[(lo + r) * k + v0 + q]; vectors at or past k are staged as 0
+    const int32_t total = nr * TV;
+    {
+        T sv[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t e = u * kThreads + int32_t(threadIdx.x);
+            const int32_t r = e / TV, q = e % TV;
+            sv[u] = e < total && v0 + q < k ? X[(lo + r) * k + v0 + q] : T(0);
+        }
+        const int m0 = wave_first(len);
+        if (rb < r1 && m0 > 0) load_grp(0, m0, wave_first(base), av[0], ac[0]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t e = u * kThreads + int32_t(threadIdx.x);
+            if (e < total) xs[e] = sv[u];
+        }
+    }
+    for (int32_t e0 = kThreads * kStage; e0 < total; e0 += kThreads * kStage) {
+        T vv[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t e = e0 + u * kThreads + int32_t(threadIdx.x);
+            const int32_t r = e / TV, q = e % TV;
+            vv[u] = e < total && v0 + q < k ? X[(lo + r) * k + v0 + q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t e = e0 + u * kThreads + int32_t(threadIdx.x);
+            if (e < total) xs[e] = vv[u];
+        }
+    }
+    __syncthreads();
+    for (bool first = true; rb < r1; rb += RP, first = false) {
+        if (!first) {
+            i = rb + lane / LPR;
+            len = i < n_pad ? row_len[i] : 0;
+            const int64_t ia = i < n_pad ? i : n_pad - 1;     // lanes past n_pad never use it
+            base = offsets[ia / BR] + (ia % BR);
+        }
         const int m = wave_first(len);
+        const int64_t base_lead = wave_first(base);         // the wave's first row is its longest
         V acc;
 #pragma unroll
         for (int q = 0; q < VPL; ++q) reinterpret_cast<T *>(&acc)[q] = T(0);
         if (m > 0) {
-            const int64_t ia = i < n_pad ? i : n_pad - 1;     // lanes past n_pad never use it
-            const int64_t base = offsets[ia / BR] + (ia % BR);
-            const int64_t base_lead = wave_first(base);   // the wave's first row is its longest
-            for (int jb = 0; jb < m; jb += U) {
-                T a_v[U];
-                int32_t a_c[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = jb + u < m ? jb + u : m - 1;     // uniform clamp past the longest row
-                    const int64_t a = (j < len ? base : base_lead) + int64_t(j) * BR;
-                    a_v[u] = ld_stream(val_p + a);
-                    a_c[u] = ld_stream(col_p + a);
-                }
+            if (!first) load_grp(0, m, base_lead, av[0], ac[0]);
+            // two register sets in turn: the next group's matrix loads go out before this
+            // group's FMAs, so they are in flight while the gathers are waited for
+            auto grp = [&](int jb, int cur) {
                 V xv[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    xv[u] = staged_or_global<V>(xs + q0, uint32_t(a_c[u]) - uint32_t(lo), uint32_t(nr), LPR, X,
-                                                int64_t(a_c[u]) * k + vc);
-                }
+                for (int u = 0; u < U; ++u)
+                    xv[u] = staged_or_global<V>(xs + q0, uint32_t(ac[cur][u]) - uint32_t(lo), uint32_t(nr), LPR, X,
+                                                int64_t(ac[cur][u]) * k + vc);
+                if (jb + U < m) load_grp(jb + U, m, base_lead, av[cur ^ 1], ac[cur ^ 1]);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool on = jb + u < len && jb + u < m;
 #pragma unroll
                     for (int q = 0; q < VPL; ++q) {
                         T &aq = reinterpret_cast<T *>(&acc)[q];
-                        const T s = __builtin_fma(a_v[u], reinterpret_cast<const T *>(&xv[u])[q], aq);
+                        const T s = __builtin_fma(av[cur][u], reinterpret_cast<const T *>(&xv[u])[q], aq);
                         aq = on ? s : aq;
                     }
                 }
+            };
+            for (int jb = 0; jb < m; jb += 2 * U) {
+                grp(jb, 0);
+                if (jb + U < m) grp(jb + U, 1);
             }
         }
         if (i < n_rows && v < k)            // Y is written once: stored non-temporally

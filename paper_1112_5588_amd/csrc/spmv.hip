@@ -710,9 +710,12 @@ __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
 // sorted row; each of them applies the row's entries to VPL adjacent right-hand sides, read
 // from the interleaved X (X[c*k + v]) with one VPL-wide load.  A matrix entry is therefore
 // loaded once per tile, a wave covers R = 64/LPR rows, and a gather instruction reads LPR *
-// VPL contiguous values per row.  Tiles over k run in gridDim.y.
+// VPL contiguous values per row.  Tiles over k run in gridDim.y; with NVT = 2 each lane also
+// takes the same place in the next vector tile (an even number of tiles and VPL = 4), so the
+// matrix is streamed once per two tiles: for each entry it gathers two VPL-wide pieces of the
+// X row and keeps two accumulators, with the same FMAs in the same order per (row, vector).
 
-template <class T, bool JD, int BR, int LPR, int VPL>
+template <class T, bool JD, int BR, int LPR, int VPL, int NVT>
 __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
     int64_t n_rows, int64_t n_pad, int64_t n_waves, int32_t k,
     const int32_t *__restrict__ row_len, const int64_t *__restrict__ offsets,
@@ -720,22 +723,26 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
     const int32_t *__restrict__ perm, const T *__restrict__ X, T *__restrict__ Y, uint32_t flags) {
     typedef typename VecOf<T, VPL>::type V;
     constexpr int R = kWave / LPR;
-    constexpr int U = VPL >= 4 ? 4 : kUnroll;
+    constexpr int U = NVT > 1 ? 2 : (VPL >= 4 ? 4 : kUnroll);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= n_waves) return;
-    // first right-hand side of this lane; k is a multiple of VPL, so a lane's VPL values are
-    // either all inside [0, k) or all outside
-    const int v = int(blockIdx.y) * (LPR * VPL) + (lane % LPR) * VPL;
-    const int vc = v < k ? v : k - VPL;
+    int v[NVT], vc[NVT];
+#pragma unroll
+    for (int n = 0; n < NVT; ++n) {
+        v[n] = (int(blockIdx.y) * NVT + n) * (LPR * VPL) + (lane % LPR) * VPL;
+        vc[n] = v[n] < k ? v[n] : k - VPL;
+    }
     const int64_t i = w * R + lane / LPR;
     const int len = i < n_pad ? row_len[i] : 0;
     const int m = wave_first(len);
-    V acc;
+    V acc[NVT];
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) reinterpret_cast<T *>(&acc)[q] = T(0);
+    for (int n = 0; n < NVT; ++n)
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) reinterpret_cast<T *>(&acc[n])[q] = T(0);
     if (m > 0) {
-        const int64_t i_lead = w * R;                      // the wave's first row is its longest
+        const int64_t i_lead = w * R;
         const PjdsAddr<JD, BR> addr{offsets};
         const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
         for (int jb = 0; jb < m; jb += U) {
@@ -743,28 +750,36 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
             int32_t a_c[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = jb + u < m ? jb + u : m - 1;      // uniform clamp past the longest row
+                const int j = jb + u < m ? jb + u : m - 1;
                 const int64_t a = addr(j, j < len ? base : base_lead);
                 a_v[u] = ld_stream(val_p + a);
                 a_c[u] = ld_stream(col_p + a);
             }
-            V xv[U];
+            V xv[U][NVT];
 #pragma unroll
-            for (int u = 0; u < U; ++u) xv[u] = *reinterpret_cast<const V *>(X + int64_t(a_c[u]) * k + vc);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int n = 0; n < NVT; ++n) xv[u][n] = *reinterpret_cast<const V *>(X + int64_t(a_c[u]) * k + vc[n]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool on = jb + u < len && jb + u < m;
 #pragma unroll
-                for (int q = 0; q < VPL; ++q) {
-                    T &aq = reinterpret_cast<T *>(&acc)[q];
-                    const T s = __builtin_fma(a_v[u], reinterpret_cast<const T *>(&xv[u])[q], aq);
-                    aq = on ? s : aq;
-                }
+                for (int n = 0; n < NVT; ++n)
+#pragma unroll
+                    for (int q = 0; q < VPL; ++q) {
+                        T &aq = reinterpret_cast<T *>(&acc[n])[q];
+                        const T s = __builtin_fma(a_v[u], reinterpret_cast<const T *>(&xv[u][n])[q], aq);
+                        aq = on ? s : aq;
+                    }
             }
         }
     }
-    if (i < n_rows && v < k)            // Y is written once: stored non-temporally
-        __builtin_nontemporal_store(acc, reinterpret_cast<V *>(Y + int64_t((flags & PJDS_Y_PERMUTED) ? i : perm[i]) * k + v));
+    if (i < n_rows) {
+        const int64_t r = (flags & PJDS_Y_PERMUTED) ? i : perm[i];
+#pragma unroll
+        for (int n = 0; n < NVT; ++n)
+            if (v[n] < k) __builtin_nontemporal_store(acc[n], reinterpret_cast<V *>(Y + r * k + v[n]));
+    }
 }
 
 // ---- ELLPACK-R, Listing 1 -------------------------------------------------------------
@@ -929,8 +944,17 @@ void launch_spmmv_lv(const pjds_info &in, const int32_t *rl, const int64_t *off,
                      const void *vp, const int32_t *perm, int32_t k, const void *X, void *Y,
                      uint32_t flags, hipStream_t s) {
     const int64_t waves = ceil_div(in.n_pad, kWave / LPR);
-    const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(ceil_div(k, LPR * VPL)));
-    hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL>), grid, dim3(kBlock), 0, s, in.n_rows,
+    const int64_t tiles = ceil_div(k, LPR * VPL);
+    if (tiles % 2 == 0 && VPL >= 4) {
+        // two vector tiles per lane: the matrix is streamed once per pair of tiles
+        const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(tiles / 2));
+        hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 2>), grid, dim3(kBlock), 0, s, in.n_rows,
+                           in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,
+                           static_cast<const T *>(X), static_cast<T *>(Y), flags);
+        return;
+    }
+    const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(tiles));
+    hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 1>), grid, dim3(kBlock), 0, s, in.n_rows,
                        in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,
                        static_cast<const T *>(X), static_cast<T *>(Y), flags);
 }

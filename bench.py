@@ -592,16 +592,25 @@ def main() -> int:
         t0_at = time.perf_counter()
         t_cat = autotune.time_all(A, x=x_orig)
         exhaustive_s = time.perf_counter() - t0_at
-        # the learned tuner on the same matrix: features on the host, one network inference
+        # the learned tuner on the same matrix: features on the host, one network inference, and
+        # on a near tie the timing of its three best candidates (the rule of tuner.decide)
         from paper_1112_5588_amd import tuner as _tn
         t0_at = time.perf_counter()
         feats = _lib.pjds_features(A.n_rows, A.n_cols, np.ascontiguousarray(A.row_ptr, np.int64),
                                    np.ascontiguousarray(A.col, np.int32))
         model = _tn.Model.load(os.path.join(ROOT, "paper_1112_5588_amd", "tuner_data", "model.json"))
-        pick_i, pick_margin = _tn.predict_matrices(model, np.asarray(feats, np.float64)[None, :],
-                                                   np.array([float(nnz)]))
+        Xf = np.asarray(feats, np.float64)[None, :]
+        runnable = autotune.runnable_mask(A.n_rows, A.n_cols, vbytes,
+                                          bool(_tn.ellr_fits(Xf, np.array([float(nnz)]))[0]))[None, :]
+        mode, cand = _tn.decide(_tn.predict_scores(model, Xf), runnable, Xf, model)
+        mode = str(mode[0])
+        if mode == "net":
+            learned_pick = autotune.CONFIG_NAMES[int(cand[0, 0])]
+        else:
+            cfgs = autotune.CATALOG if mode == "full" else [autotune.CATALOG[int(c)] for c in cand[0]]
+            t_k = autotune.time_all(A, x=x_orig, configs=cfgs)
+            learned_pick = min(t_k, key=t_k.get)
         learned_s = time.perf_counter() - t0_at
-        learned_pick = autotune.CONFIG_NAMES[int(pick_i[0])]
         lds = {}
         for sw, halo, tile in ((512, 1024, 512), (1024, 1024, 1024)):   # LDS forms outside the catalog
             Mw = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=sw)
@@ -729,7 +738,8 @@ def main() -> int:
                              "plain_GBps_alg": round(b_alg / plain / 1e6, 1),
                              "tuned_over_plain": round(plain / t_all[best], 3),
                              "exhaustive_search_s": round(exhaustive_s, 2),
-                             "learned": {"pick": learned_pick, "margin": round(float(pick_margin[0]), 4),
+                             "learned": {"pick": learned_pick, "mode": mode,
+                                         "candidates": [autotune.CONFIG_NAMES[int(c)] for c in cand[0]],
                                          "pick_ms": round(t_cat[learned_pick], 5),
                                          "regret_vs_catalog_best": round(t_cat[learned_pick] / min(t_cat.values()) - 1, 4),
                                          "over_plain": round(plain / t_cat[learned_pick], 3),

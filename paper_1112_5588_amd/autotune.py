@@ -35,10 +35,11 @@ class Config:
     x_halo: int = -1            # >= 0: x staged in LDS (pjds_spmv_xlds) with this halo
     tile_rows: int = 0          # rows per workgroup of the LDS path
     two_rows: bool = False      # two adjacent rows per lane (PJDS_TWO_ROWS)
+    lanes: int = 1              # lanes per sorted row (PJDS_LANES; block height 64 / lanes)
 
     def storage_key(self):
         if self.fmt == "pjds":
-            return ("pjds", self.block_height, self.layout, self.sort_window, self.split_len)
+            return ("pjds", self.block_height, self.layout, self.sort_window, self.split_len, self.lanes)
         return (self.fmt,)
 
 
@@ -65,7 +66,19 @@ CATALOG: tuple[Config, ...] = (
     Config("pjds_b64_w256_nosplit_2r", "pjds", 64, "block", 256, split_len=-1, two_rows=True),
     Config("pjds_b64_w256_lds768_t1024_2r", "pjds", 64, "block", 256, x_halo=768, tile_rows=1024, two_rows=True),
     Config("pjds_b64_w512_lds768_t1024_2r", "pjds", 64, "block", 512, x_halo=768, tile_rows=1024, two_rows=True),
+    # the heavy-tail entries: T lanes per sorted row (global sort, block height 64 / T), and
+    # long rows cut every 512 entries instead of the default 128
+    Config("pjds_T2_global", "pjds", 32, "block", lanes=2),
+    Config("pjds_T4_global", "pjds", 16, "block", lanes=4),
+    Config("pjds_b64_jd_split512", "pjds", 64, "jd", split_len=512),
 )
+# A record's times count for training and evaluation only if they were all taken with the
+# current timing (time_median: launches replayed from a graph, the host taken out) on the
+# current kernels, which the record marks with "times_rev" >= TIMES_REV; older records'
+# times are masked.  REVISED lists the entries whose kernels changed since the first sweep.
+REVISED = ("pjds_b64_w256_lds512", "pjds_b64_w512_lds512", "pjds_b64_w256_lds768_t1024_2r",
+           "pjds_b64_w512_lds768_t1024_2r")
+TIMES_REV = 3
 CONFIG_NAMES = tuple(c.name for c in CATALOG)
 DEFAULT = 0
 
@@ -77,24 +90,55 @@ def device_name() -> str:
     return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
 
 
-def time_median(fn, reps: int = 7, warmup: int = 2) -> float:
-    """Median milliseconds of `fn` over `reps` launches, each between two events."""
+def time_median(fn, reps: int = 7, warmup: int = 2, graph: bool = True) -> float:
+    """Median milliseconds of one launch of `fn`, with the host taken out of the timing: after
+    `warmup` eager calls (which also make anything a first call creates), `batch` calls are
+    captured in a HIP graph and the graph is replayed `reps` times between two events on the
+    stream; a replay's time over `batch` is one sample.  `batch` is sized from one eager call
+    so a replay runs about 2 ms (at most 32 calls).  Launched one by one from Python, a product
+    of a few microseconds would be timed as the binding's own overhead.  graph=False times
+    single eager calls (for a call that launches a graph of its own)."""
     for _ in range(warmup):
         fn()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for s, e in ev:
-        s.record()
-        fn()
-        e.record()
     torch.cuda.synchronize()
-    return float(np.median([s.elapsed_time(e) for s, e in ev]))
+    if not graph:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    fn()
+    s1.record()
+    torch.cuda.synchronize()
+    batch = int(min(32, max(1, 2.0 // max(s0.elapsed_time(s1), 1e-3))))
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(batch):
+                fn()
+    torch.cuda.current_stream().wait_stream(cs)
+    g.replay()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        g.replay()
+        b.record()
+    torch.cuda.synchronize()
+    del g
+    return float(np.median([a.elapsed_time(b) / batch for a, b in ev]))
 
 
 def _build(A, cfg: Config, device):
     if cfg.fmt == "pjds":
         return PjdsMatrix.from_csr(A, block_height=cfg.block_height, layout=cfg.layout,
                                    sort_window=cfg.sort_window if cfg.sort_window < A.n_rows else 0,
-                                   split_len=cfg.split_len, device=device)
+                                   split_len=cfg.split_len, device=device, lanes=cfg.lanes)
     if cfg.fmt == "ellr":
         info = EllrMatrix.plan(A)
         vb = np.asarray(A.val).dtype.itemsize
@@ -129,6 +173,24 @@ def _runner(obj, cfg: Config, x, y):
     if cfg.fmt == "ellr":
         return lambda: obj.spmv(x, y)
     return lambda: obj.spmv(x, y, variant=cfg.variant)
+
+
+def runnable_mask(n_rows: int, n_cols: int, value_bytes: int, ellr_fits: bool) -> np.ndarray:
+    """Which catalog configurations can run on a matrix of this shape, known without converting
+    or timing anything (the conditions _runner and _build apply): x staged in LDS needs a sort
+    window below n_rows that is a multiple of 256 and a staged range within 64 KiB; two rows
+    per lane without split needs windows of whole 128-row groups; ELLPACK-R its storage under
+    the size limit."""
+    ok = np.ones(len(CATALOG), dtype=bool)
+    for c, cfg in enumerate(CATALOG):
+        w = cfg.sort_window if cfg.sort_window < n_rows else 0
+        if cfg.fmt == "pjds" and cfg.x_halo >= 0:
+            ok[c] = 0 < w and w % 256 == 0 and min(max(cfg.tile_rows, w) + 2 * cfg.x_halo, n_cols) * value_bytes <= 65536
+        elif cfg.fmt == "pjds" and cfg.two_rows:
+            ok[c] = cfg.split_len < 0 and (w == 0 or w % 128 == 0)
+        elif cfg.fmt == "ellr":
+            ok[c] = bool(ellr_fits)
+    return ok
 
 
 def time_all(A, x: torch.Tensor | None = None, configs=CATALOG, reps: int = 7, warmup: int = 2,
@@ -228,6 +290,6 @@ def tune_batch(mats, xs, ys, groups=(1, 4, 8, 32), reps: int = 5) -> tuple[int, 
     t_ms = {}
     for g in groups:
         B = PjdsBatch(mats, xs, ys, mode=L.PJDS_BATCH_PERSISTENT, y_permuted=True, groups_per_tile=g)
-        t_ms[g] = time_median(B.launch, reps, 1)
+        t_ms[g] = time_median(B.launch, reps, 1, graph=False)    # the launch is a graph already
         B.close()
     return min(t_ms, key=t_ms.get), t_ms

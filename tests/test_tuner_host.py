@@ -13,7 +13,7 @@ def test_catalog_default_is_the_papers_format():
     assert c.fmt == "pjds" and c.block_height == 64 and c.layout == "jd" and c.sort_window == 0
     assert len(set(autotune.CONFIG_NAMES)) == len(autotune.CATALOG)
     keys = {c.storage_key() for c in autotune.CATALOG}
-    assert len(keys) <= 12
+    assert len(keys) <= 16          # conversions per matrix in a sweep
 
 
 def test_training_specs_are_seeded_and_cover_the_range():
@@ -35,7 +35,7 @@ def toy_records():
         if i == 2:
             t["ellr"] = None                   # not built for this matrix
         recs.append({"key": str(100000 + i), "nnz": 1000 * (i + 1), "features": list(np.arange(24) + i),
-                     "times_ms": t})
+                     "times_ms": t, "times_rev": autotune.TIMES_REV})
     return recs
 
 
@@ -104,3 +104,44 @@ def test_store_update_merges_and_compacts(tmp_path):
     st.rewrite()
     assert len(open(p).read().splitlines()) == 2
     assert tuner.load_records(p) == recs
+
+
+def test_records_timed_before_the_current_timing_are_masked():
+    recs = toy_records()
+    recs[1]["times_rev"] = autotune.TIMES_REV - 1       # an older sweep: none of its times count
+    del recs[4]["times_rev"]
+    _, y, t = tuner.arrays(recs)
+    assert np.all(np.isnan(t[[1, 4]])) and np.all(np.isnan(y[[1, 4]]))
+    assert np.isfinite(t[0]).all() and np.isfinite(t[5]).all()
+
+
+def test_decision_rule_arithmetic():
+    """The learned tuner's rule: the network's pick when it leads clearly, the fastest timed of
+    its top k on a near tie, the exhaustive search far outside the training range."""
+    X, _, t = tuner.arrays(toy_records())
+    C = len(autotune.CATALOG)
+    m = tuner.Model(np.zeros(L.mlp_param_count(24, C), np.float32), X.mean(0), X.std(0) + 1, np.zeros(C), np.ones(C))
+    runnable = np.isfinite(t)
+    best = np.where(runnable, t, np.inf).min(axis=1)
+    # scores that rank the default first with a clear lead, config 3 (the fastest) second
+    scores = np.full(t.shape, 5.0)
+    scores[:, 0], scores[:, 3] = 0.0, 1.0
+    r = tuner.evaluate_rule(scores, X, t, m, k=2, margin_min=0.5)
+    assert r["fallback_rate"] == 0.0 and r["top_k_rate"] == 0.0 and r["configs_timed_mean"] == 0.0
+    assert np.isclose(r["regret"]["max"], (t[:, 0] / best - 1).max())
+    # a near tie between the two: both are timed and the fastest measured is used
+    scores[:, 3] = 0.01
+    r = tuner.evaluate_rule(scores, X, t, m, k=2, margin_min=0.5)
+    assert r["top_k_rate"] == 1.0 and r["regret"]["max"] == 0.0 and r["configs_timed_mean"] == 2.0
+    assert np.isclose(r["regret_network"]["max"], (t[:, 0] / best - 1).max())
+    # a configuration that cannot run is never picked, however good its score
+    e = autotune.CONFIG_NAMES.index("ellr")
+    scores[:, e] = -10.0
+    mode, cand = tuner.decide(scores, runnable, X, m, k=2, margin_min=0.5)
+    assert all(cand[i, 0] == e for i in range(len(t)) if runnable[i, e])
+    assert all(cand[i, 0] != e for i in range(len(t)) if not runnable[i, e])
+    # far outside the training range: the exhaustive autotuner
+    Xo = X.copy()
+    Xo[4, 0] = m.f_mu[0] + 100 * m.f_sd[0]
+    r = tuner.evaluate_rule(scores, Xo, t, m, k=2, margin_min=0.5)
+    assert np.isclose(r["fallback_rate"], 1 / 6)

@@ -420,6 +420,8 @@ def main() -> int:
     lanes_key = f"_T{args.lanes}" if args.lanes > 1 else ""
     if args.x_halo >= 0 and args.two_rows:
         lanes_key += "_2rows"
+    if args.split_len:
+        lanes_key += f"_split{args.split_len}"
     traffic = load_traffic(f"{args.workload}_{args.dtype}_b{args.block_height}_{args.layout}_w{args.sort_window}_h{args.x_halo}_t{args.tile_rows}_{args.mode}{lanes_key}")
     result = {
         "metric": "pJDS spMVM GB/s & %HBM peak; tuned/batched vs plain GFLOP/s at <=1e-12 rel err",

@@ -80,22 +80,29 @@ __device__ __forceinline__ double block_sum_upd(double v, double *wsum) {
     for (int w = 0; w < kUpdThreads / kWave; ++w) t += wsum[w];
     return t;
 }
+// VW = 2: elements in aligned pairs, 16-byte loads and stores (n even, every vector 16-byte
+// aligned); a thread adds its elements' squares in element order either way.
+template <int VW>
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *__restrict__ w,
                                                              const double *__restrict__ v,
                                                              const double *__restrict__ dot_part, int64_t n_dot,
                                                              const double *__restrict__ inv_s,
                                                              double *__restrict__ alpha_out,
                                                              double *__restrict__ partial) {
+    typedef double Vd __attribute__((ext_vector_type(VW)));
     __shared__ double wsum[kUpdThreads / kWave];
+    const int64_t nv = n / VW;                              // VW divides n
     const int64_t stride = int64_t(kUpdBlocks) * kUpdThreads;
+    Vd *wp = reinterpret_cast<Vd *>(w);
+    const Vd *vp = reinterpret_cast<const Vd *>(v);
     int64_t i0 = blockIdx.x * int64_t(kUpdThreads) + threadIdx.x;
-    double wv[kUpdInFlight], vv[kUpdInFlight];
+    Vd wv[kUpdInFlight], vv[kUpdInFlight];
     auto load = [&](int64_t b) {
 #pragma unroll
         for (int u = 0; u < kUpdInFlight; ++u) {
             const int64_t i = b + u * stride;
-            wv[u] = i < n ? w[i] : 0.0;
-            vv[u] = i < n ? v[i] : 0.0;
+            wv[u] = i < nv ? wp[i] : Vd{};
+            vv[u] = i < nv ? vp[i] : Vd{};
         }
     };
     load(i0);
@@ -109,14 +116,19 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(int64_t n, double *
 #pragma unroll
         for (int u = 0; u < kUpdInFlight; ++u) {
             const int64_t i = i0 + u * stride;
-            if (i < n) {
-                const double wi = __builtin_fma(-a, vv[u], wv[u]);
-                w[i] = wi;
-                s = __builtin_fma(wi, wi, s);
+            if (i < nv) {
+                Vd r;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    const double wi = __builtin_fma(-a, vv[u][e], wv[u][e]);
+                    r[e] = wi;
+                    s = __builtin_fma(wi, wi, s);
+                }
+                wp[i] = r;
             }
         }
         i0 += stride * kUpdInFlight;
-        if (i0 >= n) break;
+        if (i0 >= nv) break;
         load(i0);
     }
     const double t = block_sum_upd(s, wsum);
@@ -200,6 +212,8 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
     double *inv_s = part + partial_slots(in);       // 1 / s_j
     double *zc = inv_s + 2;                         // beta_j / s_{j-1} (x through the caches)
     const bool staged = x_halo >= 0;
+    // the update in aligned pairs when every vector it touches is 16-byte aligned
+    const bool pairs = n % 2 == 0 && (reinterpret_cast<uintptr_t>(d_v0) | reinterpret_cast<uintptr_t>(V)) % 16 == 0;
     // |v|^2 as partial sums (the staged product's first step adds them itself); beta_0 = 0
     hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, d_v0, d_v0, part_nrm);
     if (!staged)
@@ -238,8 +252,12 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
             hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, w, uj, part_dot);
         }
         // alpha_j, then w -= (alpha_j / s_j) u_j with the partials of |w|^2
-        hipLaunchKernelGGL(update_kernel, dim3(kUpdBlocks), dim3(kUpdThreads), 0, s, n, w, uj, part_dot, n_dot, inv_j,
-                           d_alpha + j, part_nrm);
+        if (pairs)
+            hipLaunchKernelGGL(update_kernel<2>, dim3(kUpdBlocks), dim3(kUpdThreads), 0, s, n, w, uj, part_dot, n_dot,
+                               inv_j, d_alpha + j, part_nrm);
+        else
+            hipLaunchKernelGGL(update_kernel<1>, dim3(kUpdBlocks), dim3(kUpdThreads), 0, s, n, w, uj, part_dot, n_dot,
+                               inv_j, d_alpha + j, part_nrm);
         // beta_{j+1}: the next staged product adds the partials itself; otherwise, and after
         // the last step, one small kernel
         if (!staged || j == steps - 1)

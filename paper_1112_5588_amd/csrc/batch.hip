@@ -128,40 +128,10 @@ __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_pe
 // order per row as wave_group.
 typedef int32_t Int2 __attribute__((ext_vector_type(2)));
 
-template <int U, bool CLAMP, class T, bool JD, int BR, class XA>
-__device__ __forceinline__ void steps2(T &a0, T &a1, int jb, int m, int len0, int len1, int64_t base,
-                                       int64_t base_lead, const int64_t *__restrict__ off,
-                                       const int32_t *__restrict__ col_p, const T *__restrict__ val_p,
-                                       const XA &x) {
-    typedef typename VecOf<T, 2>::type V2;
-    V2 v[U];
-    Int2 c[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int j = CLAMP ? min(jb + u, m - 1) : jb + u;
-        const int64_t b = j < len0 ? base : base_lead;
-        const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
-        v[u] = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(val_p + a));
-        c[u] = __builtin_nontemporal_load(reinterpret_cast<const Int2 *>(col_p + a));
-    }
-    T x0[U], x1[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        x0[u] = x(c[u].x);
-        x1[u] = x(c[u].y);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const bool on = !CLAMP || jb + u < m;
-        const T s0 = __builtin_fma(v[u].x, x0[u], a0);
-        const T s1 = __builtin_fma(v[u].y, x1[u], a1);
-        a0 = (on && jb + u < len0) ? s0 : a0;
-        a1 = (on && jb + u < len1) ? s1 : a1;
-    }
-}
-
 template <class T, bool JD, int BR, class XA>
 __device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool y_perm, const XA &x) {
+    typedef typename VecOf<T, 2>::type V2;
+    constexpr int U = 4;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + 2 * lane;
     const Int2 len = i < M.n_pad ? *reinterpret_cast<const Int2 *>(M.row_len + i) : Int2{0, 0};
@@ -170,16 +140,47 @@ __device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool
     const int m = __builtin_amdgcn_readfirstlane(int(len.x));
     T a0 = T(0), a1 = T(0);
     if (m > 0) {
-        constexpr int U = 4;
         const int64_t base_lead = wave_first(base);
         const T *val_p = static_cast<const T *>(M.val_p);
-        int jb = 0;
-        for (; jb + U <= m; jb += U)
-            steps2<U, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
-        const int r = m - jb;
-        if (r > 2) steps2<4, true, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
-        else if (r == 2) steps2<2, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
-        else if (r == 1) steps2<1, false, T, JD, BR>(a0, a1, jb, m, len.x, len.y, base, base_lead, M.offsets, M.col_p, val_p, x);
+        const int64_t *__restrict__ off = M.offsets;
+        const int32_t *__restrict__ col_p = M.col_p;
+        // two register sets of U steps in turn: the next group's loads go out before this
+        // group's FMAs; steps at or past m re-read step m - 1 and are masked
+        V2 v[2][U];
+        Int2 c[2][U];
+        auto load = [&](int jb, int set) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = min(jb + u, m - 1);
+                const int64_t b = j < len.x ? base : base_lead;
+                const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
+                v[set][u] = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(val_p + a));
+                c[set][u] = __builtin_nontemporal_load(reinterpret_cast<const Int2 *>(col_p + a));
+            }
+        };
+        auto group = [&](int jb, int set) {
+            T x0[U], x1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                x0[u] = x(c[set][u].x);
+                x1[u] = x(c[set][u].y);
+            }
+            if (jb + U < m) load(jb + U, set ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool on = jb + u < m;
+                const T s0 = __builtin_fma(v[set][u].x, x0[u], a0);
+                const T s1 = __builtin_fma(v[set][u].y, x1[u], a1);
+                a0 = (on && jb + u < len.x) ? s0 : a0;
+                a1 = (on && jb + u < len.y) ? s1 : a1;
+            }
+        };
+        load(0, 0);
+        for (int jb = 0; jb < m; jb += 2 * U) {
+            group(jb, 0);
+            if (jb + U < m) group(jb + U, 1);
+        }
     }
     T *y = static_cast<T *>(M.y);
     if (i < M.n_rows) y[y_perm ? i : M.perm[i]] = a0;

@@ -458,6 +458,17 @@ int mlp_infer(const float *d_params, int32_t d_in, int32_t d_out, int64_t batch,
  * (the Infinity Cache included) held before, leaving no dirty line to write back.  d_in and
  * d_out are device arrays of n doubles (mode 1) or of n and 2048 doubles (modes 0, 2). */
 int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream);
+/* Kernel timing hook, for benchmarks (it computes nothing).  Arms the calling thread: the main
+ * kernel of the next call on this thread to pjds_spmv, pjds_spmv_xlds, pjds_spmv_noalloc,
+ * pjds_spmmv, pjds_spmmv_xlds, ellr_spmv, csr_spmv or pjds_probe (or to an entry point built
+ * on them, such as pjds_lanczos, whose first product kernel takes it) is launched with
+ * hipExtLaunchKernel, whose dispatch records `start_event` when the kernel starts and
+ * `stop_event` when it ends; hipEventElapsedTime on the two then gives the kernel's own
+ * duration, without the time the stream spends between separately recorded events and the
+ * dispatch.  Both are hipEvent_t values the caller created (hipEventCreate) and owns.  The
+ * launch that takes the events disarms the hook; (NULL, NULL) disarms it without a launch.
+ * PJDS_ERR_ARG if exactly one of the two is NULL (the hook is then left as it was). */
+int pjds_time_next_launch(void *start_event, void *stop_event);
 
 /* ---- diagnostics ------------------------------------------------------------------- */
 const char *pjds_last_error(void);

@@ -104,6 +104,7 @@ _SIGS = {
     "ellr_spmv": [_ip, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "csr_spmv": [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp],
     "pjds_probe": [_i32, _vp, _vp, _i64, _vp],
+    "pjds_time_next_launch": [_vp, _vp],
     "pjds_features": [_i64, _i64, _vp, _vp, _vp],
     "mlp_param_count": [_i32, _i32, ctypes.POINTER(_i64)],
     "mlp_workspace_size": [_i32, _i32, _i64, ctypes.POINTER(_i64)],
@@ -439,6 +440,54 @@ def pjds_probe(mode: int, d_in, d_out, n: int, stream=None) -> None:
     _dev_vec(d_in, n, PJDS_F64, "in")
     _dev_vec(d_out, n if mode == 1 else 2048, PJDS_F64, "out", like=d_in)
     _check(lib().pjds_probe(mode, _dev(d_in), _dev(d_out), n, _stream(stream)), "pjds_probe")
+
+
+def pjds_time_next_launch(start_event, stop_event) -> None:
+    """Arm the kernel timing hook with two hipEvent_t handles, or disarm it with (None, None)."""
+    _check(lib().pjds_time_next_launch(start_event, stop_event), "pjds_time_next_launch")
+
+
+class KernelTimer:
+    """Two HIP events for pjds_time_next_launch.  `arm()` before a call, `disarm()` after it;
+    once the stream has synchronized, `ms()` is the armed kernel's own duration, or None when
+    no kernel recorded the events.  The events come from the HIP runtime the library and torch
+    already share (libamdhip64.so.7)."""
+
+    _hip = None
+
+    def __init__(self):
+        if KernelTimer._hip is None:
+            h = ctypes.CDLL("libamdhip64.so.7")
+            h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+            h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+            h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+            KernelTimer._hip = h
+        self.ev = [ctypes.c_void_p(), ctypes.c_void_p()]
+        for e in self.ev:
+            rc = KernelTimer._hip.hipEventCreate(ctypes.byref(e))
+            if rc != 0:
+                raise PjdsError(PJDS_ERR_HIP, "hipEventCreate", f"error {rc}")
+
+    def arm(self) -> None:
+        pjds_time_next_launch(self.ev[0], self.ev[1])
+
+    @staticmethod
+    def disarm() -> None:
+        pjds_time_next_launch(None, None)
+
+    def ms(self):
+        out = ctypes.c_float()
+        rc = KernelTimer._hip.hipEventElapsedTime(ctypes.byref(out), self.ev[0], self.ev[1])
+        if rc != 0:
+            KernelTimer._hip.hipGetLastError()      # the failed query is no launch error
+            return None
+        return float(out.value)
+
+    def __del__(self):
+        if KernelTimer._hip is not None:
+            for e in self.ev:
+                if e.value:
+                    KernelTimer._hip.hipEventDestroy(e)
 
 
 def _batch_members(members: list, flags: int):

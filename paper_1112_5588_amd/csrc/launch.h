@@ -1,11 +1,27 @@
 // Kernel launchers shared between the HIP translation units of libpjds.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.h"
 
 namespace pjds {
+// Events armed on the calling thread by pjds_time_next_launch; taking them disarms the hook.
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+LaunchEvents take_launch_events();
+
+// Launch of an entry point's main kernel.  When the measurement hook is armed, the kernel's
+// own dispatch records the armed events at its start and end; otherwise this is an ordinary
+// launch (hipExtLaunchKernel with no events).  Errors are left for hipGetLastError.
+template <class F, class... A>
+inline void launch_main(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... a) {
+    const LaunchEvents ev = take_launch_events();
+    hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), s, ev.start, ev.stop, 0u, a...);
+}
+
 // Kernel launchers shared between translation units (spmv.hip).  The caller validates.
 // Sizes, dtype and block height of a pJDS matrix usable by the single-vector product.
 int check_product_info(const pjds_info *info, int32_t dtype);

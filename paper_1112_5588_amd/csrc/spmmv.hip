@@ -160,7 +160,7 @@ void launch_lv(const pjds_info &in, int64_t tile, int64_t halo, int32_t cap, int
                uint32_t flags, hipStream_t s) {
     const dim3 grid(unsigned(ceil_div(in.n_pad, tile)), unsigned(ceil_div(k, LPR * VPL)));
     const size_t lds = size_t(std::max(cap, 1)) * LPR * VPL * sizeof(T);
-    hipLaunchKernelGGL((spmmv_xlds_kernel<T, BR, LPR, VPL>), grid, dim3(kThreads), lds, s, in.n_rows, in.n_cols,
+    launch_main((spmmv_xlds_kernel<T, BR, LPR, VPL>), grid, dim3(kThreads), lds, s, in.n_rows, in.n_cols,
                        in.n_pad, in.sort_window, halo, tile, cap, k, rl, off, cp, static_cast<const T *>(vp), perm,
                        static_cast<const T *>(X), static_cast<T *>(Y), flags);
 }

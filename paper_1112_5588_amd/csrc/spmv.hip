@@ -923,7 +923,7 @@ void launch_pjds(const pjds_info &in, const int32_t *rl, const int64_t *off, con
     const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)));
     T *partials = static_cast<T *>(work);
     int32_t *counters = work ? reinterpret_cast<int32_t *>(static_cast<char *>(work) + ws_partials_bytes(in, sizeof(T) == 8 ? PJDS_F64 : PJDS_F32)) : nullptr;
-    hipLaunchKernelGGL((pjds_spmv_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad,
+    launch_main((pjds_spmv_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad,
                        groups, in.n_chunks, in.split_len, rl, off, cp, static_cast<const T *>(vp),
                        perm, sched, partials, counters, static_cast<const T *>(x),
                        static_cast<T *>(y), make_epi<T>(ea), flags);
@@ -934,7 +934,7 @@ void launch_pjds2(const pjds_info &in, const int32_t *rl, const int64_t *off, co
                   const int32_t *perm, const void *x, void *y, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
     const int64_t waves = ceil_div(in.n_pad, int64_t(kWave) * kRowsPerLane);
     const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)));
-    hipLaunchKernelGGL((pjds_spmv2_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad, waves, rl, off,
+    launch_main((pjds_spmv2_kernel<T, JD, BR>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_pad, waves, rl, off,
                        cp, static_cast<const T *>(vp), perm, static_cast<const T *>(x), static_cast<T *>(y),
                        make_epi<T>(ea), flags);
 }
@@ -948,13 +948,13 @@ void launch_spmmv_lv(const pjds_info &in, const int32_t *rl, const int64_t *off,
     if (tiles % 2 == 0 && VPL >= 4) {
         // two vector tiles per lane: the matrix is streamed once per pair of tiles
         const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(tiles / 2));
-        hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 2>), grid, dim3(kBlock), 0, s, in.n_rows,
+        launch_main((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 2>), grid, dim3(kBlock), 0, s, in.n_rows,
                            in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,
                            static_cast<const T *>(X), static_cast<T *>(Y), flags);
         return;
     }
     const dim3 grid(unsigned(ceil_div(waves, kWavesPerBlock)), unsigned(tiles));
-    hipLaunchKernelGGL((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 1>), grid, dim3(kBlock), 0, s, in.n_rows,
+    launch_main((pjds_spmmv_kernel<T, JD, BR, LPR, VPL, 1>), grid, dim3(kBlock), 0, s, in.n_rows,
                        in.n_pad, waves, k, rl, off, cp, static_cast<const T *>(vp), perm,
                        static_cast<const T *>(X), static_cast<T *>(Y), flags);
 }
@@ -990,7 +990,7 @@ void launch_lanes(const pjds_info &in, const int32_t *rl, const int64_t *off, co
                   const int32_t *perm, const void *x, void *y, const EpiArgs &ea, uint32_t flags, hipStream_t s) {
     const dim3 grid(unsigned(ceil_div(in.n_blocks, kWavesPerBlock)));
 #define PJDS_LANES_CASE(TL)                                                                              \
-    hipLaunchKernelGGL((pjds_lanes_kernel<T, TL>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_blocks, rl, off, \
+    launch_main((pjds_lanes_kernel<T, TL>), grid, dim3(kBlock), 0, s, in.n_rows, in.n_blocks, rl, off,        \
                        cp, static_cast<const T *>(vp), perm, static_cast<const T *>(x), static_cast<T *>(y),    \
                        make_epi<T>(ea), flags)
     switch (lanes_of(in)) {
@@ -1124,7 +1124,7 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
         const int br = in.block_height;
         if (two) {
 #define PJDS_XLDS2_LAUNCH(B, N)                                                                           \
-            hipLaunchKernelGGL((pjds_spmv_lds2_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
+            launch_main((pjds_spmv_lds2_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols,        \
                                in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,              \
                                static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),          \
                                static_cast<T *>(d_y), make_epi<T>(ea), flags)
@@ -1140,7 +1140,7 @@ void launch_xlds(const pjds_info &in, const int32_t *d_row_len, const int64_t *d
             return;
         }
 #define PJDS_XLDS_LAUNCH(B, N)                                                                            \
-        hipLaunchKernelGGL((pjds_spmv_lds_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols, \
+        launch_main((pjds_spmv_lds_kernel<T, B, N, L8>), grid, dim3(N), lds, s, in.n_rows, in.n_cols,        \
                            in.n_pad, w, int64_t(x_halo), tile, d_row_len, d_offsets, d_col_p,                  \
                            static_cast<const T *>(d_val_p), d_perm, static_cast<const T *>(d_x),              \
                            static_cast<T *>(d_y), make_epi<T>(ea), flags)
@@ -1197,6 +1197,16 @@ int scratch_address(void **out) {
     }
     *out = g_scratch_ptr[dev];
     return PJDS_OK;
+}
+
+namespace {
+thread_local LaunchEvents g_launch_events{nullptr, nullptr};
+}  // namespace
+
+LaunchEvents take_launch_events() {
+    const LaunchEvents e = g_launch_events;
+    g_launch_events = LaunchEvents{nullptr, nullptr};
+    return e;
 }
 
 }  // namespace pjds
@@ -1368,10 +1378,10 @@ int ellr_spmv(const pjds_info *info, const int32_t *d_rowmax, const int32_t *d_c
     const dim3 grid(unsigned(ceil_div(info->n_pad, kBlock)));
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dtype == PJDS_F64)
-        hipLaunchKernelGGL(ellr_spmv_kernel<double>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
+        launch_main(ellr_spmv_kernel<double>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
                            d_col_e, static_cast<const double *>(d_val_e), static_cast<const double *>(d_x), static_cast<double *>(d_y));
     else
-        hipLaunchKernelGGL(ellr_spmv_kernel<float>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
+        launch_main(ellr_spmv_kernel<float>, grid, dim3(kBlock), 0, s, info->n_rows, info->n_pad, d_rowmax,
                            d_col_e, static_cast<const float *>(d_val_e), static_cast<const float *>(d_x), static_cast<float *>(d_y));
     return launch_status("ellr_spmv");
 }
@@ -1393,10 +1403,10 @@ int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int
         const T *x = static_cast<const T *>(d_x);
         T *y = static_cast<T *>(d_y);
         switch (variant) {
-            case 1: hipLaunchKernelGGL(csr_scalar_kernel<T>, grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
-            case 4: hipLaunchKernelGGL((csr_vector_kernel<T, 4>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
-            case 16: hipLaunchKernelGGL((csr_vector_kernel<T, 16>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
-            default: hipLaunchKernelGGL((csr_vector_kernel<T, 64>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            case 1: launch_main(csr_scalar_kernel<T>, grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            case 4: launch_main((csr_vector_kernel<T, 4>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            case 16: launch_main((csr_vector_kernel<T, 16>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
+            default: launch_main((csr_vector_kernel<T, 64>), grid, dim3(kBlock), 0, s, n_rows, d_row_ptr, d_col, v, x, y); break;
         }
     };
     if (dtype == PJDS_F64) go(double{});
@@ -1404,13 +1414,19 @@ int csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t *d_row_ptr, const int
     return launch_status("csr_spmv");
 }
 
+int pjds_time_next_launch(void *start_event, void *stop_event) {
+    if (!start_event != !stop_event) return fail(PJDS_ERR_ARG, "pjds_time_next_launch: both events or neither");
+    g_launch_events = LaunchEvents{static_cast<hipEvent_t>(start_event), static_cast<hipEvent_t>(stop_event)};
+    return PJDS_OK;
+}
+
 int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void *stream) {
     if ((mode != 0 && mode != 1 && mode != 2) || n < 0 || !d_in || !d_out) return fail(PJDS_ERR_ARG, "bad probe arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid(static_cast<unsigned>(kProbeBlocks));
-    if (mode == 0) hipLaunchKernelGGL(probe_read_kernel<true>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
-    else if (mode == 2) hipLaunchKernelGGL(probe_read_kernel<false>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
-    else hipLaunchKernelGGL(probe_copy_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    if (mode == 0) launch_main(probe_read_kernel<true>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    else if (mode == 2) launch_main(probe_read_kernel<false>, grid, dim3(kBlock), 0, s, d_in, d_out, n);
+    else launch_main(probe_copy_kernel, grid, dim3(kBlock), 0, s, d_in, d_out, n);
     return launch_status("pjds_probe");
 }
 

@@ -240,3 +240,12 @@ def test_spmmv_xlds_validates_on_the_host():
     assert call(win, k=0) == L.PJDS_ERR_ARG
     # valid arguments reach the device-array check
     assert call(win) == L.PJDS_ERR_ARG and "NULL" in L.pjds_last_error()
+
+
+def test_timing_hook_is_armed_and_disarmed_on_the_host():
+    """pjds_time_next_launch takes both events or neither; it only stores them (no GPU call)."""
+    lib = L.lib()
+    assert lib.pjds_time_next_launch(ctypes.c_void_p(0x1000), None) == L.PJDS_ERR_ARG
+    assert lib.pjds_time_next_launch(None, ctypes.c_void_p(0x1000)) == L.PJDS_ERR_ARG
+    assert "both events" in L.pjds_last_error()
+    assert lib.pjds_time_next_launch(None, None) == L.PJDS_OK

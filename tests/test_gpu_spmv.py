@@ -500,3 +500,29 @@ def test_xlds_one_byte_lengths_refused_for_long_rows():
         M.spmv_xlds(xd, len8=True)
     y = M.spmv_xlds(xd)              # falls back to the int32 lengths
     assert_rows(host(y), B, synth.dense_x(3000, 32))
+
+
+def test_kernel_timing_hook_times_the_product_kernel():
+    """pjds_time_next_launch: the armed call's product kernel records both events (a duration
+    inside the events recorded around the calls), one launch takes the hook, the product is
+    unchanged, and a hook disarmed before any launch records nothing."""
+    A = synth.hh_like(1 << 16, seed=3)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=512)
+    x = dev(synth.dense_x(A.n_cols, 1))
+    y0 = M.spmv_xlds(x, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True)
+    torch.cuda.synchronize()
+    k1, k2 = L.KernelTimer(), L.KernelTimer()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    k1.arm()
+    y1 = M.spmv_xlds(x, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True)
+    y2 = M.spmv(x, y_permuted=True)         # launched after the hook was taken
+    s1.record()
+    k2.arm()
+    k2.disarm()
+    torch.cuda.synchronize()
+    t = k1.ms()
+    assert t is not None and 0 < t <= s0.elapsed_time(s1)
+    assert k2.ms() is None
+    assert torch.equal(y0, y1)
+    assert_rows(host(y2), A, synth.dense_x(A.n_cols, 1), 8, rows=M.d["perm"].cpu().numpy())

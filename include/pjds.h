@@ -467,7 +467,9 @@ int pjds_probe(int32_t mode, const double *d_in, double *d_out, int64_t n, void 
  * duration, without the time the stream spends between separately recorded events and the
  * dispatch.  Both are hipEvent_t values the caller created (hipEventCreate) and owns.  The
  * launch that takes the events disarms the hook; (NULL, NULL) disarms it without a launch.
- * PJDS_ERR_ARG if exactly one of the two is NULL (the hook is then left as it was). */
+ * Leave it disarmed while a stream is being captured into a graph: events are not graph
+ * nodes here.  PJDS_ERR_ARG if exactly one of the two is NULL (the hook is then left as it
+ * was). */
 int pjds_time_next_launch(void *start_event, void *stop_event);
 
 /* ---- diagnostics ------------------------------------------------------------------- */

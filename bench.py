@@ -681,9 +681,9 @@ def main() -> int:
             torch.cuda.current_stream().wait_stream(cs)
             ms_g = time_launches(g.replay, 5, 1)
             ys = torch.empty(n, dtype=torch.float64, device="cuda")
-            # the product as the Lanczos step runs it (int32 row lengths)
+            # the product as the Lanczos step runs it (one-byte row lengths when every row fits)
             ms_p = time_launches(lambda: Ms.spmv_xlds(v0, ys, x_halo=args.x_halo, tile_rows=args.tile_rows,
-                                                      y_permuted=True, two_rows=True, len8=False), 50, 5)
+                                                      y_permuted=True, two_rows=True), 50, 5)
             # vector passes besides the product's x and y: z read, w and u_j read and w written by
             # the update; w and u_j read once more for alpha when x is not staged in LDS
             passes = 4 if args.x_halo >= 0 else 6

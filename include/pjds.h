@@ -287,7 +287,10 @@ int pjds_spmmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64
  * Lanczos vectors are held unnormalised (v_j = u_j / s_j, the 1/s_j factors applied inside
  * the product and the updates), which saves the rescaling pass; d_v0 is only read.
  * x_halo >= 0 uses the LDS-staged product (pjds_spmv_xlds's conditions), otherwise the plain
- * one (d_sched/d_work as for pjds_spmv).  d_vectors and d_scratch are device buffers of the
+ * one (d_sched/d_work as for pjds_spmv).  flags: 0, or PJDS_ROW_LEN8 with x_halo >= 0 (the
+ * staged product then reads one-byte row lengths: d_row_len addresses the n_pad bytes
+ * pjds_pack_lengths writes; rows of at most 255 entries, else PJDS_ERR_UNSUPPORTED); any other
+ * flag, or PJDS_ROW_LEN8 without x staging, is PJDS_ERR_ARG.  d_vectors and d_scratch are device buffers of the
  * sizes pjds_lanczos_workspace reports (three vectors; reduction partials).  A zero beta
  * (invariant subspace found) makes the following steps non-finite: stop before it.
  * Reductions use a fixed grid and fixed trees: results are reproducible bit for bit.
@@ -295,8 +298,8 @@ int pjds_spmmv_xlds(const pjds_info *info, const int32_t *d_row_len, const int64
 int pjds_lanczos_workspace(const pjds_info *info, int64_t *vector_bytes, int64_t *scratch_bytes);
 int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                  const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
-                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, double *d_alpha,
-                 double *d_beta, void *d_vectors, void *d_scratch, void *stream);
+                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, uint32_t flags,
+                 double *d_alpha, double *d_beta, void *d_vectors, void *d_scratch, void *stream);
 
 /* ---- many matrices in one call ------------------------------------------------------ */
 /*

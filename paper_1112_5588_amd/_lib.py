@@ -94,7 +94,7 @@ _SIGS = {
     "pjds_spmmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "pjds_spmv_axpby": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _u32, _vp],
     "pjds_lanczos_workspace": [_ip, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
-    "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
+    "pjds_lanczos": [_ip, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp],
     "pjds_spmv_xlds": [_ip, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _u32, _vp],
     "pjds_pack_lengths": [_ip, _vp, _vp, _vp],
     "pjds_split_count": [_i64, _i64, _vp, _vp, _i64, _i64, ctypes.POINTER(_i64)],
@@ -628,9 +628,10 @@ def pjds_lanczos_workspace(info: pjds_info) -> tuple[int, int]:
 
 def pjds_lanczos(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_sched, d_work, d_v0,
                  steps: int, x_halo: int, tile_rows: int, d_alpha, d_beta, d_vectors, d_scratch,
-                 stream=None) -> None:
+                 stream=None, flags: int = 0) -> None:
     if steps > 0 and info.n_rows > 0:
-        _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, None, d_v0, d_v0, need_perm=False)
+        _pjds_operands(info, d_row_len, d_offsets, d_col_p, d_val_p, None, d_v0, d_v0, need_perm=False,
+                       len8=bool(flags & PJDS_ROW_LEN8))
         _dev_vec(d_alpha, steps, PJDS_F64, "alpha", like=d_v0)
         _dev_vec(d_beta, steps + 1, PJDS_F64, "beta", like=d_v0)
         vb, sb = pjds_lanczos_workspace(info)
@@ -638,5 +639,5 @@ def pjds_lanczos(info: pjds_info, d_row_len, d_offsets, d_col_p, d_val_p, d_sche
         _dev_vec(d_scratch, sb // 8, PJDS_F64, "scratch", like=d_v0)
     _check(lib().pjds_lanczos(ctypes.byref(info), _dev(d_row_len), _dev(d_offsets), _dev(d_col_p),
                               _dev(d_val_p), _dev(d_sched), _dev(d_work), _dev(d_v0), steps, x_halo,
-                              tile_rows, _dev(d_alpha), _dev(d_beta), _dev(d_vectors), _dev(d_scratch),
+                              tile_rows, flags, _dev(d_alpha), _dev(d_beta), _dev(d_vectors), _dev(d_scratch),
                               _stream(stream)), "pjds_lanczos")

@@ -186,13 +186,18 @@ int pjds_lanczos_workspace(const pjds_info *info, int64_t *vector_bytes, int64_t
 
 int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t *d_offsets,
                  const int32_t *d_col_p, const void *d_val_p, const int32_t *d_sched, void *d_work,
-                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, double *d_alpha,
-                 double *d_beta, void *d_vectors, void *d_scratch, void *stream) {
+                 const double *d_v0, int32_t steps, int32_t x_halo, int32_t tile_rows, uint32_t flags,
+                 double *d_alpha, double *d_beta, void *d_vectors, void *d_scratch, void *stream) {
     if (int rc = check_product_info(info, PJDS_F64)) return rc;
     const pjds_info &in = *info;
     if (!(in.flags & PJDS_SYMMETRIC) || in.n_rows != in.n_cols)
         return fail(PJDS_ERR_ARG, "Lanczos needs a square matrix converted with PJDS_SYMMETRIC");
     if (steps < 0) return fail(PJDS_ERR_ARG, "steps %d", steps);
+    if (flags & ~PJDS_ROW_LEN8) return fail(PJDS_ERR_ARG, "unknown Lanczos flags 0x%x", flags);
+    if ((flags & PJDS_ROW_LEN8) && x_halo < 0)
+        return fail(PJDS_ERR_ARG, "PJDS_ROW_LEN8 needs the staged product (x_halo >= 0)");
+    if ((flags & PJDS_ROW_LEN8) && in.max_row_len > 255)
+        return fail(PJDS_ERR_UNSUPPORTED, "PJDS_ROW_LEN8 with rows of %d entries (at most 255)", in.max_row_len);
     if (x_halo >= 0) {
         if (int rc = check_xlds(in, PJDS_F64, x_halo, tile_rows)) return rc;
     } else if (in.n_chunks && (!d_sched || !d_work)) {
@@ -242,7 +247,7 @@ int pjds_lanczos(const pjds_info *info, const int32_t *d_row_len, const int64_t 
             ea.dot_partial = part_dot;
             n_dot = xlds_tiles(in, tile_rows);
             launch_xlds(in, d_row_len, d_offsets, d_col_p, d_val_p, nullptr, PJDS_F64, uj, w, x_halo, tile_rows, ea,
-                        PJDS_Y_PERMUTED | PJDS_TWO_ROWS, s);
+                        PJDS_Y_PERMUTED | PJDS_TWO_ROWS | (flags & PJDS_ROW_LEN8), s);
         } else {
             ea.alpha_dev = inv_j;
             ea.beta_dev = zc + (j & 1);

@@ -119,18 +119,25 @@ class PjdsMatrix:
 
     def lanczos(self, v0: torch.Tensor, steps: int, x_halo: int = -1, tile_rows: int = 0,
                 alpha: torch.Tensor | None = None, beta: torch.Tensor | None = None,
-                buffers: dict | None = None, stream=None):
+                buffers: dict | None = None, stream=None, len8: bool | None = None):
         """Lanczos coefficients (alpha [steps], beta [steps+1]) from start vector v0, given in the
-        permuted basis; the matrix must have been converted with symmetric=True."""
+        permuted basis; the matrix must have been converted with symmetric=True.  len8: the
+        staged product (x_halo >= 0) reads the one-byte row lengths (None: whenever it can)."""
         if alpha is None:
             alpha = torch.empty(max(steps, 1), dtype=torch.float64, device=self.device)
         if beta is None:
             beta = torch.empty(steps + 1, dtype=torch.float64, device=self.device)
         b = buffers or self.lanczos_buffers()
         d = self.d
-        L.pjds_lanczos(self.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"],
+        if x_halo >= 0:
+            rl, flags = self._staged_lengths(len8)
+        elif len8:
+            raise ValueError("one-byte row lengths need the staged product (x_halo >= 0)")
+        else:
+            rl, flags = d["row_len"], 0
+        L.pjds_lanczos(self.info, rl, d["offsets"], d["col_p"], d["val_p"],
                        d["sched"] if self.info.n_chunks else None, d["work"], v0, steps, x_halo, tile_rows,
-                       alpha, beta, b["vectors"], b["scratch"], stream)
+                       alpha, beta, b["vectors"], b["scratch"], stream, flags=flags)
         return alpha[:steps], beta
 
     def row_len8(self) -> torch.Tensor | None:
@@ -139,10 +146,29 @@ class PjdsMatrix:
         if self.info.max_row_len > 255:
             return None
         if "row_len8" not in self.d:
+            if torch.cuda.is_current_stream_capturing():
+                # made inside a graph, the copy would hold its lengths only after a replay
+                raise RuntimeError("make the one-byte row lengths (row_len8()) before capturing a graph")
             t = torch.empty(max(self.info.n_pad, 1), dtype=torch.uint8, device=self.device)
             L.pjds_pack_lengths(self.info, self.d["row_len"], t)
             self.d["row_len8"] = t
         return self.d["row_len8"]
+
+    def _staged_lengths(self, len8: bool | None):
+        """The row lengths a staged product reads and the flag that says which: the one-byte
+        copy when len8 is True, the int32 array when False; None takes the copy whenever every
+        row fits a byte and the copy exists or can be made now (not while a graph is being
+        captured)."""
+        if len8 is False:
+            return self.d["row_len"], 0
+        if len8 is None and "row_len8" not in self.d and torch.cuda.is_current_stream_capturing():
+            return self.d["row_len"], 0
+        r8 = self.row_len8()
+        if r8 is None:
+            if len8:
+                raise ValueError(f"rows of {self.info.max_row_len} entries do not fit one-byte lengths")
+            return self.d["row_len"], 0
+        return r8, L.PJDS_ROW_LEN8
 
     def spmv_xlds(self, x: torch.Tensor, y: torch.Tensor | None = None, x_halo: int = 512,
                   tile_rows: int = 0, y_permuted: bool = False, xcd_remap: bool = False,
@@ -155,13 +181,8 @@ class PjdsMatrix:
         flags = (L.PJDS_Y_PERMUTED if y_permuted else 0) | (L.PJDS_XCD_REMAP if xcd_remap else 0)
         flags |= L.PJDS_TWO_ROWS if two_rows else 0
         d = self.d
-        rl = d["row_len"]
-        if len8 is None or len8:
-            r8 = self.row_len8()
-            if r8 is None and len8:
-                raise ValueError(f"rows of {self.info.max_row_len} entries do not fit one-byte lengths")
-            if r8 is not None:
-                rl, flags = r8, flags | L.PJDS_ROW_LEN8
+        rl, f8 = self._staged_lengths(len8)
+        flags |= f8
         L.pjds_spmv_xlds(self.info, rl, d["offsets"], d["col_p"], d["val_p"], d["perm"], x, y,
                          x_halo, tile_rows, flags, stream)
         return y

@@ -249,3 +249,22 @@ def test_timing_hook_is_armed_and_disarmed_on_the_host():
     assert lib.pjds_time_next_launch(None, ctypes.c_void_p(0x1000)) == L.PJDS_ERR_ARG
     assert "both events" in L.pjds_last_error()
     assert lib.pjds_time_next_launch(None, None) == L.PJDS_OK
+
+
+def test_lanczos_flags_are_checked_on_the_host():
+    """pjds_lanczos takes PJDS_ROW_LEN8 only with the staged product, and no other flag; both
+    refusals come before any device array is looked at."""
+    A = synth.laplacian_2d(32)
+    info = L.pjds_plan(A.n_rows, A.n_cols, A.row_ptr, 64, 256, L.PJDS_LAYOUT_BLOCK | L.PJDS_SYMMETRIC)
+    lib = L.lib()
+    args = (None, None, None, None, None, None, None, 3)
+    assert lib.pjds_lanczos(ctypes.byref(info), *args, -1, 0, L.PJDS_ROW_LEN8, None, None, None, None,
+                            None) == L.PJDS_ERR_ARG
+    assert "x_halo" in L.pjds_last_error()
+    assert lib.pjds_lanczos(ctypes.byref(info), *args, 256, 256, 0x100, None, None, None, None,
+                            None) == L.PJDS_ERR_ARG
+    assert "flags" in L.pjds_last_error()
+    # accepted flags get as far as the NULL arrays
+    assert lib.pjds_lanczos(ctypes.byref(info), *args, 256, 256, L.PJDS_ROW_LEN8, None, None, None, None,
+                            None) == L.PJDS_ERR_ARG
+    assert "NULL" in L.pjds_last_error()

@@ -127,3 +127,34 @@ def test_lanczos_is_deterministic_and_graph_capturable():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(alpha, ref_a) and torch.equal(beta, ref_b), rep
+
+
+def test_lanczos_one_byte_lengths_are_bitwise_the_int32_ones():
+    """The staged Lanczos product reading one-byte row lengths gives the same coefficients bit
+    for bit; under graph capture with no one-byte copy made yet, the default keeps the int32
+    lengths (the copy would exist only inside the graph)."""
+    A = synth.hh_like(40000, seed=17)
+    M = PjdsMatrix.from_csr(A, symmetric=True, layout="block", sort_window=512, keep_host=True)
+    v0 = dev(synth.dense_x(A.n_cols, 17)[M.host["perm"]])
+    bufs = M.lanczos_buffers()
+    a32 = torch.empty(10, dtype=torch.float64, device="cuda")
+    b32 = torch.empty(11, dtype=torch.float64, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            M.lanczos(v0, 10, x_halo=768, tile_rows=1024, alpha=a32, beta=b32, buffers=bufs)
+    torch.cuda.current_stream().wait_stream(s)
+    assert "row_len8" not in M.d
+    g.replay()
+    torch.cuda.synchronize()
+    a8, b8 = M.lanczos(v0, 10, x_halo=768, tile_rows=1024, len8=True)
+    ai, bi = M.lanczos(v0, 10, x_halo=768, tile_rows=1024, len8=False)
+    assert torch.equal(a8, ai) and torch.equal(b8, bi)
+    assert torch.equal(a32, ai) and torch.equal(b32, bi)
+    ra, rb = krylov.lanczos(A, synth.dense_x(A.n_cols, 17), 10)
+    assert np.allclose(host(a8), ra, rtol=1e-8, atol=1e-10)
+    assert np.allclose(host(b8), rb, rtol=1e-8, atol=1e-10)
+    with pytest.raises(ValueError):
+        M.lanczos(v0, 10, x_halo=-1, len8=True)

@@ -102,7 +102,7 @@ def test_symmetric_permuted_basis(y_permuted):
     check_pjds(A, synth.dense_x(50000, 9), symmetric=True, y_permuted=y_permuted)
 
 
-@pytest.mark.parametrize("split_len", [-1, 64, 128, 256])
+@pytest.mark.parametrize("split_len", [-1, 64, 128, 256, 512])
 @pytest.mark.parametrize("b_r", [32, 64, 128])
 def test_long_rows_split(split_len, b_r):
     A = synth.powerlaw(1 << 16, seed=6, l_max=4096)

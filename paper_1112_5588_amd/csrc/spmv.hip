@@ -714,6 +714,8 @@ __global__ void zero_ints_kernel(int32_t *p, int64_t n) {
 // takes the same place in the next vector tile (an even number of tiles and VPL = 4), so the
 // matrix is streamed once per two tiles: for each entry it gathers two VPL-wide pieces of the
 // X row and keeps two accumulators, with the same FMAs in the same order per (row, vector).
+// Steps run in groups of U with two register sets in turn, so a group's value and index loads
+// are in flight while the group before it gathers X.
 
 template <class T, bool JD, int BR, int LPR, int VPL, int NVT>
 __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
@@ -745,21 +747,28 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
         const int64_t i_lead = w * R;
         const PjdsAddr<JD, BR> addr{offsets};
         const int64_t base = addr.base(i), base_lead = addr.base(i_lead);
-        for (int jb = 0; jb < m; jb += U) {
-            T a_v[U];
-            int32_t a_c[U];
+        // two register sets of U steps in turn: a group's X gathers go out, then the next
+        // group's value and index loads, then the group's FMAs
+        T a_v[2][U];
+        int32_t a_c[2][U];
+        auto load = [&](int jb, int set) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = jb + u < m ? jb + u : m - 1;
                 const int64_t a = addr(j, j < len ? base : base_lead);
-                a_v[u] = ld_stream(val_p + a);
-                a_c[u] = ld_stream(col_p + a);
+                a_v[set][u] = ld_stream(val_p + a);
+                a_c[set][u] = ld_stream(col_p + a);
             }
+        };
+        auto group = [&](int jb, int set) {
             V xv[U][NVT];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int n = 0; n < NVT; ++n) xv[u][n] = *reinterpret_cast<const V *>(X + int64_t(a_c[u]) * k + vc[n]);
+                for (int n = 0; n < NVT; ++n)
+                    xv[u][n] = *reinterpret_cast<const V *>(X + int64_t(a_c[set][u]) * k + vc[n]);
+            if (jb + U < m) load(jb + U, set ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool on = jb + u < len && jb + u < m;
@@ -768,10 +777,15 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
 #pragma unroll
                     for (int q = 0; q < VPL; ++q) {
                         T &aq = reinterpret_cast<T *>(&acc[n])[q];
-                        const T s = __builtin_fma(a_v[u], reinterpret_cast<const T *>(&xv[u][n])[q], aq);
+                        const T s = __builtin_fma(a_v[set][u], reinterpret_cast<const T *>(&xv[u][n])[q], aq);
                         aq = on ? s : aq;
                     }
             }
+        };
+        load(0, 0);
+        for (int jb = 0; jb < m; jb += 2 * U) {
+            group(jb, 0);
+            if (jb + U < m) group(jb + U, 1);
         }
     }
     if (i < n_rows) {

@@ -225,62 +225,15 @@ struct VecR { typedef T type __attribute__((ext_vector_type(R))); };
 template <int R>
 struct IdxR { typedef int32_t type __attribute__((ext_vector_type(R))); };
 
-template <int U, bool CLAMP, int R, class T, class Addr, class XR>
-__device__ __forceinline__ void row_steps_r(T (&acc)[R], int jb, int j1, const int (&len)[R], int64_t base,
-                                            int64_t base_lead, const Addr &addr, const int32_t *__restrict__ col_p,
-                                            const T *__restrict__ val_p, const XR &xr) {
-    typedef typename VecR<T, R>::type V;
-    typedef typename IdxR<R>::type I;
-    V v[U];
-    I c[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int j = CLAMP ? min(jb + u, j1 - 1) : jb + u;
-        const int64_t a = addr(j, j < len[0] ? base : base_lead);
-        v[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(val_p + a));
-        c[u] = __builtin_nontemporal_load(reinterpret_cast<const I *>(col_p + a));
-    }
-    T xv[U][R];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int q = 0; q < R; ++q) xv[u][q] = xr(c[u][q]);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const bool on = !CLAMP || jb + u < j1;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const T s = __builtin_fma(v[u][q], xv[u][q], acc[q]);
-            acc[q] = (on && jb + u < len[q]) ? s : acc[q];
-        }
-    }
-}
-
-// All R rows' sums over steps [0, j1): full groups, then one clamped group.
-template <int R, class T, class Addr, class XR>
-__device__ __forceinline__ void row_group_sum(T (&acc)[R], int64_t base, int64_t base_lead, const int (&len)[R], int j1,
-                                              const Addr &addr, const int32_t *__restrict__ col_p,
-                                              const T *__restrict__ val_p, const XR &xr) {
-    constexpr int U = R >= 4 ? 2 : 4;                // 8 entries in flight per lane
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = T(0);
-    int jb = 0;
-    for (; jb + U <= j1; jb += U) row_steps_r<U, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
-    const int r = j1 - jb;
-    if (r > 2) row_steps_r<4, true, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
-    else if (r == 2) row_steps_r<2, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
-    else if (r == 1) row_steps_r<1, false, R>(acc, jb, j1, len, base, base_lead, addr, col_p, val_p, xr);
-}
-
 // R rows per lane with the next group of steps loading while the current one gathers: the
 // values and indices of steps [jb + U, jb + 2U) are issued after the gathers of steps
 // [jb, jb + U) and before their FMAs, so a wave keeps a group of matrix loads in flight while
 // it waits for x.  The loop body is one block with a fixed number of loads behind the
 // gathers, so the FMAs wait for the gathers only.  Every group is U steps wide; steps at or
 // past the wave's longest row m re-read step m - 1 (lines already fetched) and are masked,
-// so no load reaches past the longest row.  Same FMAs in the same order per row as
-// row_group_sum.  The caller loads the first group (steps [0, U)) into ga, so it can issue
-// those loads early, before work that does not depend on them.
+// so no load reaches past the longest row.  One FMA per entry in stored order per row, as in
+// row_steps.  The caller loads the first group (steps [0, U)) into ga, so it can issue those
+// loads early, before work that does not depend on them.
 template <int U, int R, class T>
 struct StepGroup {
     typedef typename VecR<T, R>::type V;
@@ -432,7 +385,10 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv2_kernel(
     for (int q = 0; q < R; ++q) len[q] = lv[q];
     const int m = wave_first(len[0]);
     T acc[R];
-    row_group_sum<R>(acc, base, wave_first(base), len, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
+    StepGroup<(R >= 4 ? 2 : 4), R, T> g0;      // first group of steps, then two sets in turn
+    const int64_t bl = wave_first(base);
+    if (m > 0) g0.load(0, m, len[0], base, bl, addr, col_p, val_p);
+    row_group_sum_pipe<R>(acc, g0, base, bl, len, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
     const bool y_perm = flags & PJDS_Y_PERMUTED;
 #pragma unroll
     for (int q = 0; q < R; ++q)

@@ -145,3 +145,14 @@ def test_decision_rule_arithmetic():
     Xo[4, 0] = m.f_mu[0] + 100 * m.f_sd[0]
     r = tuner.evaluate_rule(scores, Xo, t, m, k=2, margin_min=0.5)
     assert np.isclose(r["fallback_rate"], 1 / 6)
+
+
+def test_partial_retime_takes_only_records_one_revision_behind():
+    """Re-timing a subset of the catalog upgrades only records whose other times are current;
+    re-timing every entry takes every older record."""
+    rev = autotune.TIMES_REV
+    recs = {("1", "d"): {"times_rev": rev}, ("2", "d"): {"times_rev": rev - 1}, ("3", "d"): {},
+            ("4", "d"): {"times_rev": rev - 2}, ("5", "e"): {"times_rev": rev - 1}}
+    seeds = [1, 2, 3, 4, 5, 6]
+    assert tuner.retime_todo(recs, seeds, "d", every_config=False) == [2]
+    assert tuner.retime_todo(recs, seeds, "d", every_config=True) == [2, 3, 4]

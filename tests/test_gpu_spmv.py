@@ -526,3 +526,51 @@ def test_kernel_timing_hook_times_the_product_kernel():
     assert k2.ms() is None
     assert torch.equal(y0, y1)
     assert_rows(host(y2), A, synth.dense_x(A.n_cols, 1), 8, rows=M.d["perm"].cpu().numpy())
+
+
+def test_timing_hook_is_taken_by_every_one_kernel_entry_point():
+    """Each one-kernel product entry point (and the probe) launches its main kernel with the
+    armed events; a call refused on the host launches nothing and leaves the hook armed for
+    the next launch."""
+    A = synth.hh_like(1 << 15, seed=4)
+    x = synth.dense_x(A.n_cols, 4)
+    xd = dev(x)
+    M = PjdsMatrix.from_csr(A, block_height=64, layout="block", sort_window=512)
+    X = dev(synth.dense_x(A.n_cols, 4, k=4).reshape(A.n_cols, 4))
+    E, C = EllrMatrix.from_csr(A), CsrMatrix.from_csr(A)
+    buf = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    out = torch.empty(2048, dtype=torch.float64, device="cuda")
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+    d = M.d
+    calls = {
+        "pjds_spmv": lambda: M.spmv(xd, y_permuted=True),
+        "pjds_spmv_xlds": lambda: M.spmv_xlds(xd, x_halo=768, tile_rows=1024, y_permuted=True, two_rows=True),
+        "pjds_spmv_noalloc": lambda: L.pjds_spmv_noalloc(M.info, d["row_len"], d["offsets"], d["col_p"], d["val_p"],
+                                                         d["perm"], d["sched"] if M.info.n_chunks else None, xd, y, L.PJDS_Y_PERMUTED),
+        "pjds_spmmv": lambda: M.spmmv(X, y_permuted=True),
+        "pjds_spmmv_xlds": lambda: M.spmmv_xlds(X, x_halo=512, tile_rows=1024, y_permuted=True),
+        "ellr_spmv": lambda: E.spmv(xd),
+        "csr_spmv": lambda: C.spmv(xd, variant=4),
+        "pjds_probe": lambda: L.pjds_probe(0, buf, out, 1 << 20),
+    }
+    timers = {}
+    for name, fn in calls.items():
+        t = L.KernelTimer()
+        t.arm()
+        fn()
+        t.disarm()
+        timers[name] = t
+    torch.cuda.synchronize()
+    for name, t in timers.items():
+        ms = t.ms()
+        assert ms is not None and ms > 0, name
+    # a refused call takes nothing: the next launch records the events
+    t = L.KernelTimer()
+    t.arm()
+    with pytest.raises(Exception):
+        M.spmv(xd[: A.n_cols // 2])                 # x too short: refused before any launch
+    M.spmv(xd, y_permuted=True)
+    t.disarm()
+    torch.cuda.synchronize()
+    assert t.ms() is not None
+    assert_rows(host(M.spmv(xd, y_permuted=True)), A, x, 8, rows=d["perm"].cpu().numpy())

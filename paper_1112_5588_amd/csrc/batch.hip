@@ -103,8 +103,9 @@ template <class T, bool JD, int BR, class XA>
 __device__ __forceinline__ void wave_group(const Member &M, int64_t g, bool y_perm, const XA &x) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + lane;
-    const int len = i < M.n_pad ? M.row_len[i] : 0;
+    int len = M.row_len[i < M.n_pad ? i : M.n_pad - 1];          // clamped, then masked
     const int64_t base = JD ? i : M.offsets[(i < M.n_pad ? i : M.n_pad - 1) / BR] + (i % BR);
+    if (i >= M.n_pad) len = 0;
     const int m = __builtin_amdgcn_readfirstlane(len);
     T acc = T(0);
     if (m > 0) {
@@ -132,8 +133,9 @@ __device__ __forceinline__ void wave_group_pipe(const Member &M, int64_t g, bool
     constexpr int U = kUnroll;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + lane;
-    const int len = i < M.n_pad ? M.row_len[i] : 0;
+    int len = M.row_len[i < M.n_pad ? i : M.n_pad - 1];          // clamped, then masked
     const int64_t base = JD ? i : M.offsets[(i < M.n_pad ? i : M.n_pad - 1) / BR] + (i % BR);
+    if (i >= M.n_pad) len = 0;
     const int m = __builtin_amdgcn_readfirstlane(len);
     T acc = T(0);
     if (m > 0) {
@@ -186,8 +188,9 @@ __device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool
     constexpr int U = 4;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t i = g * kWave + 2 * lane;
-    const Int2 len = i < M.n_pad ? *reinterpret_cast<const Int2 *>(M.row_len + i) : Int2{0, 0};
     const int64_t ia = i < M.n_pad ? i : M.n_pad - 2;
+    Int2 len = *reinterpret_cast<const Int2 *>(M.row_len + ia);   // clamped, then masked
+    if (i >= M.n_pad) len = Int2{0, 0};
     const int64_t base = JD ? ia : M.offsets[ia / BR] + (ia % BR);
     const int m = __builtin_amdgcn_readfirstlane(int(len.x));
     T a0 = T(0), a1 = T(0);

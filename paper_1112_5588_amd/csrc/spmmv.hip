@@ -63,9 +63,10 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     int32_t ac[2][U];
     int64_t rb = r0 + int64_t(threadIdx.x >> 6) * RW;
     int64_t i = rb + lane / LPR;
-    int len = i < n_pad ? row_len[i] : 0;
     const int64_t ia0 = i < n_pad ? i : n_pad - 1;
+    int len = row_len[ia0];                              // clamped, then masked
     int64_t base = offsets[ia0 / BR] + (ia0 % BR);
+    if (i >= n_pad) len = 0;
     auto load_grp = [&](int jb, int m_, int64_t bl, T (&a_v)[U], int32_t (&a_c)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -112,9 +113,10 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     for (bool first = true; rb < r1; rb += RP, first = false) {
         if (!first) {
             i = rb + lane / LPR;
-            len = i < n_pad ? row_len[i] : 0;
             const int64_t ia = i < n_pad ? i : n_pad - 1;     // lanes past n_pad never use it
+            len = row_len[ia];
             base = offsets[ia / BR] + (ia % BR);
+            if (i >= n_pad) len = 0;
         }
         const int m = wave_first(len);
         const int64_t base_lead = wave_first(base);         // the wave's first row is its longest

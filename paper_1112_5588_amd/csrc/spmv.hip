@@ -324,8 +324,9 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
         const int32_t g = sched[4 * w + 0], c = sched[4 * w + 1], nc = sched[4 * w + 2], first = sched[4 * w + 3];
         const int64_t i = int64_t(g) * kWave + lane;
         const PjdsAddr<JD, BR> addr{offsets};
-        const int len = i < n_pad ? row_len[i] : 0;
+        int len = row_len[i < n_pad ? i : n_pad - 1];      // clamped, then masked (see below)
         const int64_t base = addr.base(i);
+        if (i >= n_pad) len = 0;
         const int m = wave_first(len);
         const int j0 = c * split_len, j1 = min(j0 + split_len, m);
         const T part = row_range_sum(base, wave_first(base), len, j0, j1, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
@@ -351,12 +352,17 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv_kernel(
     if (g >= n_groups) return;
     const int64_t i = g * kWave + lane;
     const PjdsAddr<JD, BR> addr{offsets};
-    const int len = i < n_pad ? row_len[i] : 0;
+    // the length loads at an index clamped into range and is masked afterwards, and no early
+    // exit sits between it and the offset load: both are in flight together (a load in a
+    // branch, or one the compiler may sink below a branch, costs a round trip of its own)
+    int len = row_len[i < n_pad ? i : n_pad - 1];
     const int64_t base = addr.base(i);
+    if (i >= n_pad) len = 0;
     const int m = wave_first(len);
-    if (split_len > 0 && m > split_len) return;            // done by the work items above
-    const T acc = row_range_sum(base, wave_first(base), len, 0, m, addr, col_p, val_p, XGlobal<T>{x, 1, 0});
-    if (i < n_rows) {
+    const bool by_items = split_len > 0 && m > split_len;  // done by the work items above
+    const T acc = row_range_sum(base, wave_first(base), len, 0, by_items ? 0 : m, addr, col_p, val_p,
+                                XGlobal<T>{x, 1, 0});
+    if (!by_items && i < n_rows) {
         const int64_t r = y_perm ? i : perm[i];
         epi.store(y, r, acc);
     }
@@ -377,7 +383,8 @@ __global__ __launch_bounds__(kBlock) void pjds_spmv2_kernel(
     const int64_t w = int64_t(logical_block(flags)) * kWavesPerBlock + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     const int64_t i = w * (kWave * R) + int64_t(R) * lane;
-    const I lv = i < n_pad ? *reinterpret_cast<const I *>(row_len + i) : I{};
+    I lv = *reinterpret_cast<const I *>(row_len + (i < n_pad ? i : n_pad - R));   // clamped, then masked
+    if (i >= n_pad) lv = I{};
     const PjdsAddr<JD, BR> addr{offsets};
     const int64_t base = addr.base(i < n_pad ? i : n_pad - R);    // n_pad is a multiple of R
     int len[R];
@@ -443,8 +450,9 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
     // address the last real row, so the offsets are never read out of range.
     const PjdsAddr<false, BR> addr{offsets};
     int64_t i = r0 + threadIdx.x;
-    int len = i < n_pad ? row_len_at<L8>(row_len, i) : 0;
+    int len = row_len_at<L8>(row_len, i < n_pad ? i : n_pad - 1);     // clamped, then masked
     int64_t base = addr.base(i < n_pad ? i : n_pad - 1);
+    if (i >= n_pad) len = 0;
     // copy x[lo, hi) with kStage independent loads in flight per thread
     for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += int64_t(NT) * kStage) {
         T v[kStage];
@@ -472,8 +480,9 @@ __global__ __launch_bounds__(NT) void pjds_spmv_lds_kernel(
         rb += NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
         i = rb + threadIdx.x;
-        len = i < n_pad ? row_len_at<L8>(row_len, i) : 0;
+        len = row_len_at<L8>(row_len, i < n_pad ? i : n_pad - 1);
         base = addr.base(i < n_pad ? i : n_pad - 1);
+        if (i >= n_pad) len = 0;
     }
 }
 
@@ -500,8 +509,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void pj
     // n_pad is a multiple of R, so a group never straddles it; groups past it address the
     // last real group
     int64_t i = r0 + R * int64_t(threadIdx.x);
-    I lv = i < n_pad ? row_len_pair<L8>(row_len, i) : I{};
+    // the lengths load at an index clamped into range and are masked afterwards: a load in a
+    // branch would have to land (and be unpacked) inside it, before anything else is issued
+    I lv = row_len_pair<L8>(row_len, i < n_pad ? i : n_pad - R);
     int64_t base = addr.base(i < n_pad ? i : n_pad - R);
+    if (i >= n_pad) lv = I{};
     // a Lanczos step: this thread's share of the previous pass's partial sums, loaded with the
     // copy of x and added up after it
     double npart = 0.0;
@@ -596,8 +608,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void pj
         rb += int64_t(R) * NT;
         if (rb >= r0 + tile || rb >= n_pad) break;
         i = rb + R * int64_t(threadIdx.x);
-        lv = i < n_pad ? row_len_pair<L8>(row_len, i) : I{};
+        lv = row_len_pair<L8>(row_len, i < n_pad ? i : n_pad - R);
         base = addr.base(i < n_pad ? i : n_pad - R);
+        if (i >= n_pad) lv = I{};
     }
     if (epi.dot) {
         // fixed-order workgroup sum: butterfly inside each wave, then the waves in order
@@ -692,7 +705,8 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
         vc[n] = v[n] < k ? v[n] : k - VPL;
     }
     const int64_t i = w * R + lane / LPR;
-    const int len = i < n_pad ? row_len[i] : 0;
+    int len = row_len[i < n_pad ? i : n_pad - 1];        // clamped, then masked
+    if (i >= n_pad) len = 0;
     const int m = wave_first(len);
     V acc[NVT];
 #pragma unroll

@@ -79,14 +79,16 @@ __device__ __forceinline__ void steps(T &acc, int jb, int m, int len, int64_t ba
                                       const T *__restrict__ val_p, const XA &x) {
     T v[U];
     int32_t c[U];
+    int64_t a[U];                                      // indices first, then values
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = CLAMP ? min(jb + u, m - 1) : jb + u;
         const int64_t b = j < len ? base : base_lead;   // lead row: an entry at every such j
-        const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
-        v[u] = ld_stream(val_p + a);
-        c[u] = ld_stream(col_p + a);
+        a[u] = JD ? off[j] + b : b + int64_t(j) * BR;
+        c[u] = ld_stream(col_p + a[u]);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ld_stream(val_p + a[u]);
     T xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) xv[u] = x(c[u]);
@@ -146,14 +148,16 @@ __device__ __forceinline__ void wave_group_pipe(const Member &M, int64_t g, bool
         T v[2][U];
         int32_t c[2][U];
         auto load = [&](int jb, int set) {
+            int64_t a[U];                              // indices first, then values
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = min(jb + u, m - 1);
                 const int64_t b = j < len ? base : base_lead;   // lead row: an entry at every such j
-                const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
-                v[set][u] = ld_stream(val_p + a);
-                c[set][u] = ld_stream(col_p + a);
+                a[u] = JD ? off[j] + b : b + int64_t(j) * BR;
+                c[set][u] = ld_stream(col_p + a[u]);
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[set][u] = ld_stream(val_p + a[u]);
         };
         auto group = [&](int jb, int set) {
             T xv[U];
@@ -204,14 +208,17 @@ __device__ __forceinline__ void wave_group_pair(const Member &M, int64_t g, bool
         V2 v[2][U];
         Int2 c[2][U];
         auto load = [&](int jb, int set) {
+            int64_t a[U];                              // indices first, then values
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = min(jb + u, m - 1);
                 const int64_t b = j < len.x ? base : base_lead;
-                const int64_t a = JD ? off[j] + b : b + int64_t(j) * BR;
-                v[set][u] = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(val_p + a));
-                c[set][u] = __builtin_nontemporal_load(reinterpret_cast<const Int2 *>(col_p + a));
+                a[u] = JD ? off[j] + b : b + int64_t(j) * BR;
+                c[set][u] = __builtin_nontemporal_load(reinterpret_cast<const Int2 *>(col_p + a[u]));
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[set][u] = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(val_p + a[u]));
         };
         auto group = [&](int jb, int set) {
             T x0[U], x1[U];

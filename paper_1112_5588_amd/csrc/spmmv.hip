@@ -68,13 +68,15 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     int64_t base = offsets[ia0 / BR] + (ia0 % BR);
     if (i >= n_pad) len = 0;
     auto load_grp = [&](int jb, int m_, int64_t bl, T (&a_v)[U], int32_t (&a_c)[U]) {
+        int64_t a[U];                                    // indices first, then values
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = jb + u < m_ ? jb + u : m_ - 1;     // uniform clamp past the longest row
-            const int64_t a = (j < len ? base : bl) + int64_t(j) * BR;
-            a_v[u] = ld_stream(val_p + a);
-            a_c[u] = ld_stream(col_p + a);
+            a[u] = (j < len ? base : bl) + int64_t(j) * BR;
+            a_c[u] = ld_stream(col_p + a[u]);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) a_v[u] = ld_stream(val_p + a[u]);
     };
     // xs[r * TV + q] = X[(lo + r) * k + v0 + q]; vectors at or past k are staged as 0
     const int32_t total = nr * TV;

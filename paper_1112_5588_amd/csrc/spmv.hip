@@ -176,13 +176,15 @@ __device__ __forceinline__ void row_steps(T &acc, int jb, int j1, int len, int64
                                           const T *__restrict__ val_p, const XR &xr) {
     T v[U];
     int32_t c[U];
+    int64_t a[U];                                      // indices first, then values
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = CLAMP ? min(jb + u, j1 - 1) : jb + u;
-        const int64_t a = addr(j, j < len ? base : base_lead);
-        v[u] = ld_stream(val_p + a);
-        c[u] = ld_stream(col_p + a);
+        a[u] = addr(j, j < len ? base : base_lead);
+        c[u] = ld_stream(col_p + a[u]);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ld_stream(val_p + a[u]);
     T xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) xv[u] = xr(c[u]);
@@ -243,13 +245,16 @@ struct StepGroup {
     template <class Addr>
     __device__ __forceinline__ void load(int jb, int m, int len0, int64_t base, int64_t base_lead, const Addr &addr,
                                          const int32_t *__restrict__ col_p, const T *__restrict__ val_p) {
+        // the indices first: the gathers wait for them only, the values can still be in flight
+        int64_t a[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = min(jb + u, m - 1);
-            const int64_t a = addr(j, j < len0 ? base : base_lead);
-            v[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(val_p + a));
-            c[u] = __builtin_nontemporal_load(reinterpret_cast<const I *>(col_p + a));
+            a[u] = addr(j, j < len0 ? base : base_lead);
+            c[u] = __builtin_nontemporal_load(reinterpret_cast<const I *>(col_p + a[u]));
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(val_p + a[u]));
     }
     template <class XR>
     __device__ __forceinline__ void gather(T (&xv)[U * R], const XR &xr) const {
@@ -722,13 +727,15 @@ __global__ __launch_bounds__(kBlock) void pjds_spmmv_kernel(
         T a_v[2][U];
         int32_t a_c[2][U];
         auto load = [&](int jb, int set) {
+            int64_t a[U];                              // indices first, then values
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = jb + u < m ? jb + u : m - 1;
-                const int64_t a = addr(j, j < len ? base : base_lead);
-                a_v[set][u] = ld_stream(val_p + a);
-                a_c[set][u] = ld_stream(col_p + a);
+                a[u] = addr(j, j < len ? base : base_lead);
+                a_c[set][u] = ld_stream(col_p + a[u]);
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) a_v[set][u] = ld_stream(val_p + a[u]);
         };
         auto group = [&](int jb, int set) {
             V xv[U][NVT];

@@ -81,9 +81,12 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     // xs[r * TV + q] = X[(lo + r) * k + v0 + q]; vectors at or past k are staged as 0
     const int32_t total = nr * TV;
     {
-        T sv[kStage];
+        // the first kPre chunks of the copy in registers, then the first matrix group, then
+        // the LDS writes: all of these loads are in flight together
+        constexpr int kPre = 2;
+        T sv[kPre * kStage];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
+        for (int u = 0; u < kPre * kStage; ++u) {
             const int32_t e = u * kThreads + int32_t(threadIdx.x);
             const int32_t r = e / TV, q = e % TV;
             sv[u] = e < total && v0 + q < k ? X[(lo + r) * k + v0 + q] : T(0);
@@ -92,12 +95,12 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
         if (rb < r1 && m0 > 0) load_grp(0, m0, wave_first(base), av[0], ac[0]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
+        for (int u = 0; u < kPre * kStage; ++u) {
             const int32_t e = u * kThreads + int32_t(threadIdx.x);
             if (e < total) xs[e] = sv[u];
         }
     }
-    for (int32_t e0 = kThreads * kStage; e0 < total; e0 += kThreads * kStage) {
+    for (int32_t e0 = kThreads * kStage * 2; e0 < total; e0 += kThreads * kStage) {
         T vv[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {

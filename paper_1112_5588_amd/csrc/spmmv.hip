@@ -80,10 +80,10 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
     };
     // xs[r * TV + q] = X[(lo + r) * k + v0 + q]; vectors at or past k are staged as 0
     const int32_t total = nr * TV;
+    // the first kPre chunks of the copy in registers, then the first matrix group, then the
+    // LDS writes: all of these loads are in flight together
+    constexpr int kPre = 2;
     {
-        // the first kPre chunks of the copy in registers, then the first matrix group, then
-        // the LDS writes: all of these loads are in flight together
-        constexpr int kPre = 2;
         T sv[kPre * kStage];
 #pragma unroll
         for (int u = 0; u < kPre * kStage; ++u) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void spmmv_xlds_kernel(
             if (e < total) xs[e] = sv[u];
         }
     }
-    for (int32_t e0 = kThreads * kStage * 2; e0 < total; e0 += kThreads * kStage) {
+    for (int32_t e0 = kThreads * kStage * kPre; e0 < total; e0 += kThreads * kStage) {
         T vv[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
